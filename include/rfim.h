@@ -1,0 +1,174 @@
+/*
+ * rfim.h -- C ABI of librfim.so: Exchange Monte Carlo (parallel tempering)
+ * for the 3D random field Ising model on one AMD Instinct MI355X (gfx950).
+ *
+ * The method (Navarro, Huang, Deng, "Adaptive Multi-GPU Exchange Monte Carlo
+ * for the 3D Random Field Ising Model", arXiv:1508.06268):
+ *   - H = -J sum_<ij> s_i s_j - h sum_i h_i s_i on a periodic L^3 lattice,
+ *     each bond counted once (Sec. 1, Eq. 1);
+ *   - R replicas of one disorder realization at temperatures T_1 < ... < T_R,
+ *     each evolved by checkerboard Metropolis sweeps: sites with
+ *     (x+y+z) mod 2 = 0 first, then the others (Sec. 3.1 step 4, Sec. 3.2,
+ *     Eq. 3);
+ *   - every `exchange_every` sweeps, the per-replica energies are reduced
+ *     and adjacent temperature slots (p, p+1) with p = k (mod 2) try to swap
+ *     with probability min(1, e^Delta), Delta = (b_{p+1}-b_p)(E_{p+1}-E_p)
+ *     (Sec. 3.1, Eq. 2, read with the Hukushima-Nemoto sign); temperatures
+ *     move, configurations stay (Sec. 3.3);
+ *   - adaptive insertion of temperatures at the midpoints of the intervals
+ *     with the lowest exchange rates after short trial runs (Sec. 4).
+ *
+ * Conventions the paper leaves open, fixed here (and identical in the test
+ * oracle, so that runs with +-1 fields are reproducible bit for bit):
+ *   site i = x + L*(y + L*z); sublattice index j = i >> 1;
+ *   Philox4x32-10, key = (lo32(seed), hi32(seed)), counter word 3 =
+ *   (tag << 28) | realization;
+ *     initial spins:  tag 1, ctr = (i >> 2, 0, r),      word i & 3, s = +1 iff >= 2^31;
+ *     sweep t, col c: tag 2, ctr = (j >> 2, 2t + c, r), word j & 3 = u32;
+ *     exchange k:     tag 3, ctr = (p, k, 0), U53 = ((w0 >> 11) 2^32 + w1) 2^-53;
+ *   +-1 fields: accept iff dE <= 0 or u32 < min(floor(exp(-beta dE) 2^32), 2^32-1),
+ *   thresholds built in FP64 on the host; energies exact integers;
+ *   other fields: dE and exp(-beta dE) in FP32 on the device (rare decisions
+ *   may differ from an FP64 evaluation; energies are FP64 sums).
+ *
+ * Ownership and threading.  The caller owns every host array; inputs are
+ * copied, outputs are written into caller buffers of the documented size.
+ * A handle owns its device memory and issues all work on one HIP stream
+ * (its own, or one set with rfim_set_stream).  One handle is used from one
+ * thread at a time; different handles are independent.
+ *
+ * Errors.  Calls return RFIM_OK (0) or a negative status; constructors
+ * return NULL.  rfim_last_error() gives a thread-local message for the last
+ * failure.  Arguments are validated before any device work.  A kernel fault
+ * surfaces as RFIM_EDEVICE at the next call that synchronizes.
+ */
+#ifndef RFIM_H
+#define RFIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rfim rfim_t;
+
+enum {
+    RFIM_OK = 0,
+    RFIM_EINVAL = -1,   /* bad argument */
+    RFIM_ENOMEM = -2,   /* device or host allocation failed */
+    RFIM_EDEVICE = -3,  /* HIP runtime or kernel error */
+    RFIM_ESTATE = -4,   /* call not valid in the handle's state */
+    RFIM_ECAP = -5,     /* beyond a capacity (R_cap, sweep counter 2^31-1) */
+    RFIM_EBUSY = -6     /* pool budget exhausted (batch/serving calls) */
+};
+
+enum { RFIM_FIELDS_AUTO = -1, RFIM_FIELDS_BIMODAL = 0, RFIM_FIELDS_CONTINUOUS = 1 };
+
+/*
+ * Create one realization (Sec. 3.1 steps 1-3).
+ *   L       even, 2 <= L <= 1024 (odd L breaks the periodic checkerboard).
+ *   R       number of replicas / temperature slots, 1 <= R <= 65536.
+ *   J, h    coupling and field strength, finite.
+ *   fields  host [L^3] float, natural site order, finite.  Bimodal (exact
+ *           integer path) iff every value is exactly +1 or -1.
+ *   temps   host [R] double, finite, > 0, strictly ascending.
+ *   seed    64-bit Philox key.  Realization id 0.
+ * Returns NULL on failure (see rfim_last_error()).
+ */
+rfim_t *rfim_create(int L, int R, double J, double h, const float *fields,
+                    const double *temps, uint64_t seed);
+
+typedef struct rfim_params {
+    int L, R;
+    int R_cap;              /* >= R; capacity for adaptive growth (0 = R) */
+    double J, h;
+    const float *fields;    /* host [L^3] */
+    const double *temps;    /* host [R] */
+    uint64_t seed;
+    uint32_t realization;   /* < 2^28; selects an independent stream */
+    int field_kind;         /* RFIM_FIELDS_AUTO / _BIMODAL / _CONTINUOUS */
+} rfim_params_t;
+
+/* As rfim_create with the extra parameters; hip_stream is a hipStream_t
+ * owned by the caller (NULL: the handle creates its own). */
+rfim_t *rfim_create_ex(const rfim_params_t *params, void *hip_stream);
+
+/*
+ * n sweeps of all replicas; after every sweep that makes the global sweep
+ * count a multiple of exchange_every (> 0), the energies are reduced and one
+ * exchange step runs (Sec. 3.1 step 4).  exchange_every = 0: no exchange.
+ * Asynchronous on the handle's stream.  RFIM_ECAP if the global sweep count
+ * would pass 2^31 - 1.
+ */
+int rfim_sweep(rfim_t *h, int64_t n, int exchange_every);
+
+/* Energies E[R] by temperature slot (ascending T), reduced on the device
+ * from the current state.  Synchronizes. */
+int rfim_energies(rfim_t *h, double *E);
+
+/*
+ * Adaptive temperatures (Sec. 4).  For each of `trials` trial runs: zero the
+ * exchange counters, run sweeps_per_trial sweeps with exchange every
+ * exchange_every (> 0) continuing the chain, compute each pair's rate
+ * acc/att, and insert at most max_insert_per_trial new temperatures at the
+ * midpoints (T_p + T_{p+1})/2 of the lowest-rate intervals (ties to the lower
+ * slot) whose rate is below rate_threshold, while R stays <= R_cap.  A new
+ * replica starts as a copy of the replica at the colder end p and gets the
+ * next replica id.  Counters are zeroed after each insertion.
+ * R_cap must not exceed the capacity given at creation.  Returns the new R
+ * (>= 1) or a negative status.  Synchronizes.
+ */
+int rfim_adapt_temps(rfim_t *h, int trials, int64_t sweeps_per_trial,
+                     int exchange_every, double rate_threshold,
+                     int max_insert_per_trial, int R_cap);
+
+/* Release the handle and its device memory.  NULL-safe.  Synchronizes. */
+void rfim_destroy(rfim_t *h);
+
+/* Thread-local message for the last failure on this thread. */
+const char *rfim_last_error(void);
+
+/* ---- additions: streams, observables, state, checkpoint ---- */
+
+/* Issue future work on hip_stream (a hipStream_t owned by the caller, or
+ * NULL for the handle's own stream).  Orders itself after pending work. */
+int rfim_set_stream(rfim_t *h, void *hip_stream);
+/* Block until the handle's pending work is done; RFIM_EDEVICE on fault. */
+int rfim_synchronize(rfim_t *h);
+
+int rfim_num_replicas(const rfim_t *h);
+int rfim_lattice_size(const rfim_t *h);
+int rfim_field_kind(const rfim_t *h);
+/* Temperatures [R] by slot, ascending. */
+int rfim_temps(const rfim_t *h, double *T);
+/* Magnetisations M[R] = sum_i s_i by slot.  Synchronizes. */
+int rfim_magnetizations(rfim_t *h, int64_t *M);
+/* Energy pieces by replica id: bond sum B[R], field sum F[R] (FP64; exact
+ * integers for +-1 fields), magnetisation M[R].  Synchronizes. */
+int rfim_components(rfim_t *h, int64_t *B, double *F, int64_t *M);
+/* Spins [R][L^3] (+-1, natural site order) by replica id.  Synchronizes. */
+int rfim_get_spins(rfim_t *h, int8_t *s);
+int rfim_set_spins(rfim_t *h, const int8_t *s);
+/* Slot -> replica permutation t2r[R]. */
+int rfim_get_perm(rfim_t *h, int32_t *t2r);
+int rfim_set_perm(rfim_t *h, const int32_t *t2r);
+/* Global sweep counter t and exchange counter k. */
+int rfim_get_counters(rfim_t *h, uint64_t *t, uint64_t *k);
+int rfim_set_counters(rfim_t *h, uint64_t t, uint64_t k);
+/* Exchange attempts/acceptances per lower slot p, arrays of R-1. */
+int rfim_exchange_stats(rfim_t *h, uint64_t *att, uint64_t *acc);
+int rfim_reset_exchange_stats(rfim_t *h);
+
+/* Checkpoint: the whole chain state (parameters, fields, temperatures,
+ * spins, permutation, counters, exchange statistics) as a byte blob.
+ * rfim_save with buf == NULL stores the needed size in *len.  A handle
+ * restored with rfim_load continues the chain bit for bit. */
+int rfim_save(rfim_t *h, void *buf, size_t *len);
+rfim_t *rfim_load(const void *buf, size_t len, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,761 @@
+// Host runtime and C ABI of librfim.so (see include/rfim.h).  Validates
+// arguments, owns device memory and the stream, builds the acceptance
+// tables, sequences the sweep / energy / exchange kernels, and runs the
+// adaptive temperature insertion of Sec. 4 between trial runs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <queue>
+#include <string>
+#include <vector>
+
+#include "rfim.h"
+#include "rfim_internal.h"
+
+using rfim_dev::Lattice;
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(RFIM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));         \
+    } while (0)
+
+constexpr int kMaxR = 65536;
+constexpr uint64_t kMaxSweeps = 0x7FFFFFFFull;
+
+}  // namespace
+
+struct rfim {
+    // parameters
+    int L = 0, N = 0, half = 0, R = 0, R_cap = 0, log2L = -1, kind = 0;
+    double J = 0, h = 0;
+    uint64_t seed = 0;
+    uint32_t rho = 0;
+    std::vector<float> fields;      // natural order, as given
+    std::vector<double> T;          // by slot
+    uint32_t always_mask = 0;
+    // host mirrors of the device counters
+    uint64_t t = 0, k = 0;
+    // stream
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    // device memory
+    uint8_t *d_spins = nullptr, *d_fbits = nullptr;
+    float *d_fhf = nullptr, *d_fraw = nullptr, *d_betaf = nullptr;
+    uint32_t *d_thr = nullptr;
+    double *d_beta = nullptr, *d_part = nullptr, *d_E = nullptr;
+    int32_t *d_t2r = nullptr, *d_r2t = nullptr;
+    uint64_t *d_att = nullptr, *d_acc = nullptr, *d_ctrs = nullptr;
+    int64_t *d_B = nullptr, *d_M = nullptr;
+    double *d_F = nullptr;
+    int nblk = 1;
+
+    Lattice lattice() const {
+        Lattice a;
+        a.L = L;
+        a.N = N;
+        a.half = half;
+        a.R = R;
+        a.log2L = log2L;
+        a.kind = kind;
+        a.Jf = (float)J;
+        a.J = J;
+        a.h = h;
+        a.key0 = (uint32_t)seed;
+        a.key1 = (uint32_t)(seed >> 32);
+        a.rho = rho;
+        a.always_mask = always_mask;
+        a.spins = d_spins;
+        a.fbits = d_fbits;
+        a.fhf = d_fhf;
+        a.fraw = d_fraw;
+        a.thr = d_thr;
+        a.betaf = d_betaf;
+        a.beta = d_beta;
+        a.t2r = d_t2r;
+        a.r2t = d_r2t;
+        a.att = d_att;
+        a.acc = d_acc;
+        a.ctrs = d_ctrs;
+        a.part = d_part;
+        a.nblk = nblk;
+        a.E = d_E;
+        return a;
+    }
+};
+
+namespace {
+
+void free_device(rfim *h) {
+    void *ptrs[] = {h->d_spins, h->d_fbits, h->d_fhf, h->d_fraw, h->d_betaf, h->d_thr,
+                    h->d_beta,  h->d_part,  h->d_E,   h->d_t2r,  h->d_r2t,   h->d_att,
+                    h->d_acc,   h->d_ctrs,  h->d_B,   h->d_M,    h->d_F};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+}
+
+int validate(const rfim_params_t *p, int *kind_out) {
+    if (!p) return fail(RFIM_EINVAL, "params is NULL");
+    if (p->L < 2 || p->L > 1024 || (p->L & 1))
+        return fail(RFIM_EINVAL, "L must be even with 2 <= L <= 1024 (got %d)", p->L);
+    const int R_cap = p->R_cap == 0 ? p->R : p->R_cap;
+    if (p->R < 1 || p->R > kMaxR) return fail(RFIM_EINVAL, "R must be in [1, %d] (got %d)", kMaxR, p->R);
+    if (R_cap < p->R || R_cap > kMaxR)
+        return fail(RFIM_EINVAL, "R_cap must be in [R, %d] (got %d)", kMaxR, R_cap);
+    if (!p->fields || !p->temps) return fail(RFIM_EINVAL, "fields and temps must not be NULL");
+    if (!std::isfinite(p->J) || !std::isfinite(p->h)) return fail(RFIM_EINVAL, "J and h must be finite");
+    if (p->realization >= (1u << 28)) return fail(RFIM_EINVAL, "realization id must be < 2^28");
+    for (int t = 0; t < p->R; ++t) {
+        if (!std::isfinite(p->temps[t]) || !(p->temps[t] > 0.0))
+            return fail(RFIM_EINVAL, "temps must be finite and > 0 (temps[%d])", t);
+        if (t > 0 && !(p->temps[t] > p->temps[t - 1]))
+            return fail(RFIM_EINVAL, "temps must be strictly ascending (temps[%d])", t);
+    }
+    const size_t N = (size_t)p->L * p->L * p->L;
+    bool bimodal = true;
+    for (size_t i = 0; i < N; ++i) {
+        const float f = p->fields[i];
+        if (!std::isfinite(f)) return fail(RFIM_EINVAL, "fields must be finite (fields[%zu])", i);
+        if (f != 1.0f && f != -1.0f) bimodal = false;
+    }
+    int kind;
+    if (p->field_kind == RFIM_FIELDS_AUTO) kind = bimodal ? 0 : 1;
+    else if (p->field_kind == RFIM_FIELDS_BIMODAL || p->field_kind == RFIM_FIELDS_CONTINUOUS) kind = p->field_kind;
+    else return fail(RFIM_EINVAL, "field_kind must be -1, 0 or 1");
+    if (kind == 0 && !bimodal) return fail(RFIM_EINVAL, "bimodal field kind needs every field = +-1");
+    *kind_out = kind;
+    return RFIM_OK;
+}
+
+// Metropolis thresholds for +-1 fields (class = 2k + fb, dE = 2(J a + h b),
+// a = 2k - 6, b = 2 fb - 1), FP64 on the host: floor(exp(-beta dE) 2^32)
+// clamped to 2^32 - 1; classes with dE <= 0 are always accepted.
+double class_delta(const rfim *h, int cls) {
+    const int a = 2 * (cls >> 1) - 6;
+    const int b = 2 * (cls & 1) - 1;
+    return 2.0 * (h->J * (double)a + h->h * (double)b);
+}
+
+int upload_tables(rfim *h) {
+    std::vector<uint32_t> thr((size_t)h->R * 16, 0u);
+    std::vector<double> beta(h->R);
+    std::vector<float> betaf(h->R);
+    uint32_t mask = 0;
+    for (int c = 0; c < 14; ++c)
+        if (class_delta(h, c) <= 0.0) mask |= 1u << c;
+    h->always_mask = mask;
+    for (int t = 0; t < h->R; ++t) {
+        beta[t] = 1.0 / h->T[t];
+        betaf[t] = (float)beta[t];
+        for (int c = 0; c < 14; ++c) {
+            if (mask & (1u << c)) {
+                thr[(size_t)t * 16 + c] = 0xFFFFFFFFu;
+                continue;
+            }
+            const double scaled = std::ldexp(std::exp(-(beta[t] * class_delta(h, c))), 32);
+            thr[(size_t)t * 16 + c] = scaled >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)std::floor(scaled);
+        }
+    }
+    HIPCHK(hipMemcpyAsync(h->d_thr, thr.data(), thr.size() * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->d_beta, beta.data(), beta.size() * 8, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->d_betaf, betaf.data(), betaf.size() * 4, hipMemcpyHostToDevice, h->stream));
+    // pageable sources: make sure the copies are consumed before the vectors die
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return RFIM_OK;
+}
+
+// Natural site order <-> colour-split layout (index only, no arithmetic of
+// the method): site i of colour c goes to [c][i >> 1].
+template <class F>
+void for_each_site(int L, F f) {
+    const size_t N = (size_t)L * L * L;
+    for (size_t i = 0; i < N; ++i) {
+        const int x = (int)(i % L), y = (int)((i / L) % L), z = (int)(i / ((size_t)L * L));
+        f(i, (x + y + z) & 1, i >> 1);
+    }
+}
+
+int alloc_device(rfim *h) {
+    const size_t N = (size_t)h->N, half = N / 2, Rc = (size_t)h->R_cap;
+    h->nblk = rfim_dev::energy_blocks_per_replica(h->L);
+#define ALLOC(ptr, bytes)                                                                \
+    do {                                                                                 \
+        hipError_t e_ = hipMalloc((void **)&(ptr), (bytes));                             \
+        if (e_ != hipSuccess) return fail(RFIM_ENOMEM, "hipMalloc(%zu): %s", (size_t)(bytes), hipGetErrorString(e_)); \
+    } while (0)
+    ALLOC(h->d_spins, Rc * N);
+    if (h->kind == 0) {
+        ALLOC(h->d_fbits, N);
+    } else {
+        ALLOC(h->d_fhf, N * sizeof(float));
+        ALLOC(h->d_fraw, N * sizeof(float));
+    }
+    ALLOC(h->d_thr, Rc * 16 * sizeof(uint32_t));
+    ALLOC(h->d_betaf, Rc * sizeof(float));
+    ALLOC(h->d_beta, Rc * sizeof(double));
+    ALLOC(h->d_t2r, Rc * sizeof(int32_t));
+    ALLOC(h->d_r2t, Rc * sizeof(int32_t));
+    ALLOC(h->d_att, Rc * sizeof(uint64_t));
+    ALLOC(h->d_acc, Rc * sizeof(uint64_t));
+    ALLOC(h->d_ctrs, 2 * sizeof(uint64_t));
+    ALLOC(h->d_part, Rc * (size_t)h->nblk * 3 * sizeof(double));
+    ALLOC(h->d_E, Rc * sizeof(double));
+    ALLOC(h->d_B, Rc * sizeof(int64_t));
+    ALLOC(h->d_M, Rc * sizeof(int64_t));
+    ALLOC(h->d_F, Rc * sizeof(double));
+#undef ALLOC
+    (void)half;
+    return RFIM_OK;
+}
+
+int upload_fields(rfim *h) {
+    const size_t N = (size_t)h->N, half = N / 2;
+    if (h->kind == 0) {
+        std::vector<uint8_t> fb(N);
+        for_each_site(h->L, [&](size_t i, int c, size_t j) { fb[c * half + j] = h->fields[i] > 0.0f ? 1 : 0; });
+        HIPCHK(hipMemcpyAsync(h->d_fbits, fb.data(), N, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    } else {
+        std::vector<float> hf(N), raw(N);
+        for_each_site(h->L, [&](size_t i, int c, size_t j) {
+            raw[c * half + j] = h->fields[i];
+            hf[c * half + j] = (float)(h->h * (double)h->fields[i]);
+        });
+        HIPCHK(hipMemcpyAsync(h->d_fhf, hf.data(), N * 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->d_fraw, raw.data(), N * 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    return RFIM_OK;
+}
+
+int upload_perm(rfim *h, const std::vector<int32_t> &t2r) {
+    std::vector<int32_t> r2t(h->R);
+    for (int t = 0; t < h->R; ++t) r2t[t2r[t]] = t;
+    HIPCHK(hipMemcpyAsync(h->d_t2r, t2r.data(), h->R * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->d_r2t, r2t.data(), h->R * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return RFIM_OK;
+}
+
+int upload_counters(rfim *h) {
+    uint64_t c[2] = {h->t, h->k};
+    HIPCHK(hipMemcpyAsync(h->d_ctrs, c, sizeof c, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return RFIM_OK;
+}
+
+int reset_stats(rfim *h) {
+    HIPCHK(hipMemsetAsync(h->d_att, 0, (size_t)h->R_cap * 8, h->stream));
+    HIPCHK(hipMemsetAsync(h->d_acc, 0, (size_t)h->R_cap * 8, h->stream));
+    return RFIM_OK;
+}
+
+int download_perm(rfim *h, std::vector<int32_t> &t2r) {
+    t2r.resize(h->R);
+    HIPCHK(hipMemcpyAsync(t2r.data(), h->d_t2r, h->R * 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return RFIM_OK;
+}
+
+int compute_components(rfim *h) {
+    Lattice lat = h->lattice();
+    HIPCHK(rfim_dev::launch_energy(lat, h->stream));
+    HIPCHK(rfim_dev::launch_reduce(lat, h->d_B, h->d_F, h->d_M, h->stream));
+    return RFIM_OK;
+}
+
+rfim *create_impl(const rfim_params_t *p, void *stream, int *err) {
+    int kind = 0;
+    *err = validate(p, &kind);
+    if (*err) return nullptr;
+    rfim *h = new (std::nothrow) rfim();
+    if (!h) {
+        *err = fail(RFIM_ENOMEM, "out of host memory");
+        return nullptr;
+    }
+    h->L = p->L;
+    h->N = p->L * p->L * p->L;
+    h->half = h->N / 2;
+    h->R = p->R;
+    h->R_cap = p->R_cap == 0 ? p->R : p->R_cap;
+    h->kind = kind;
+    h->J = p->J;
+    h->h = p->h;
+    h->seed = p->seed;
+    h->rho = p->realization;
+    h->log2L = -1;
+    if (p->L >= 8 && (p->L & (p->L - 1)) == 0) {
+        int l = 0;
+        while ((1 << l) < p->L) ++l;
+        h->log2L = l;
+    }
+    h->fields.assign(p->fields, p->fields + h->N);
+    h->T.assign(p->temps, p->temps + p->R);
+    if (stream) {
+        h->stream = (hipStream_t)stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            *err = fail(RFIM_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+            delete h;
+            return nullptr;
+        }
+        h->own_stream = true;
+    }
+    return h;
+}
+
+int init_device(rfim *h) {
+    int rc;
+    if ((rc = alloc_device(h))) return rc;
+    if ((rc = upload_fields(h))) return rc;
+    if ((rc = upload_tables(h))) return rc;
+    std::vector<int32_t> ident(h->R);
+    for (int t = 0; t < h->R; ++t) ident[t] = t;
+    if ((rc = upload_perm(h, ident))) return rc;
+    if ((rc = upload_counters(h))) return rc;
+    if ((rc = reset_stats(h))) return rc;
+    HIPCHK(rfim_dev::launch_init(h->lattice(), 0, h->R, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return RFIM_OK;
+}
+
+void destroy_impl(rfim *h) {
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    free_device(h);
+    if (h->own_stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+int sweep_impl(rfim *h, int64_t n, int every) {
+    Lattice lat = h->lattice();
+    int64_t remaining = n;
+    while (remaining > 0) {
+        int64_t to_next = every > 0 ? (int64_t)(every - (int64_t)(h->t % (uint64_t)every)) : remaining;
+        const int m = (int)std::min<int64_t>(remaining, to_next);
+        for (int q = 0; q < m; ++q) {
+            HIPCHK(rfim_dev::launch_sweep(lat, 0, q, h->stream));
+            HIPCHK(rfim_dev::launch_sweep(lat, 1, q, h->stream));
+        }
+        if (every > 0 && m == to_next) {
+            HIPCHK(rfim_dev::launch_energy(lat, h->stream));
+            HIPCHK(rfim_dev::launch_exchange(lat, m, h->stream));
+            h->k += 1;
+        } else {
+            HIPCHK(rfim_dev::launch_advance(lat, m, h->stream));
+        }
+        h->t += (uint64_t)m;
+        remaining -= m;
+    }
+    return RFIM_OK;
+}
+
+}  // namespace
+
+// ===================================================================
+// C ABI
+// ===================================================================
+extern "C" {
+
+const char *rfim_last_error(void) { return g_error.c_str(); }
+
+rfim_t *rfim_create_ex(const rfim_params_t *params, void *hip_stream) {
+    int err = 0;
+    rfim *h = create_impl(params, hip_stream, &err);
+    if (!h) return nullptr;
+    if (init_device(h)) {
+        std::string msg = g_error;
+        destroy_impl(h);
+        g_error = msg;
+        return nullptr;
+    }
+    return h;
+}
+
+rfim_t *rfim_create(int L, int R, double J, double h, const float *fields, const double *temps,
+                    uint64_t seed) {
+    rfim_params_t p;
+    std::memset(&p, 0, sizeof p);
+    p.L = L;
+    p.R = R;
+    p.R_cap = R;
+    p.J = J;
+    p.h = h;
+    p.fields = fields;
+    p.temps = temps;
+    p.seed = seed;
+    p.realization = 0;
+    p.field_kind = RFIM_FIELDS_AUTO;
+    return rfim_create_ex(&p, nullptr);
+}
+
+void rfim_destroy(rfim_t *h) { destroy_impl(h); }
+
+int rfim_set_stream(rfim_t *h, void *hip_stream) {
+    if (!h) return fail(RFIM_EINVAL, "handle is NULL");
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (h->own_stream && hip_stream) {
+        HIPCHK(hipStreamDestroy(h->stream));
+        h->own_stream = false;
+        h->stream = (hipStream_t)hip_stream;
+    } else if (hip_stream) {
+        h->stream = (hipStream_t)hip_stream;
+    } else if (!h->own_stream) {
+        HIPCHK(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+        h->own_stream = true;
+    }
+    return RFIM_OK;
+}
+
+int rfim_synchronize(rfim_t *h) {
+    if (!h) return fail(RFIM_EINVAL, "handle is NULL");
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return RFIM_OK;
+}
+
+int rfim_sweep(rfim_t *h, int64_t n, int exchange_every) {
+    if (!h) return fail(RFIM_EINVAL, "handle is NULL");
+    if (n < 0 || exchange_every < 0) return fail(RFIM_EINVAL, "n and exchange_every must be >= 0");
+    if (h->t + (uint64_t)n > kMaxSweeps) return fail(RFIM_ECAP, "global sweep counter would pass 2^31-1");
+    return sweep_impl(h, n, exchange_every);
+}
+
+int rfim_num_replicas(const rfim_t *h) { return h ? h->R : fail(RFIM_EINVAL, "handle is NULL"); }
+int rfim_lattice_size(const rfim_t *h) { return h ? h->L : fail(RFIM_EINVAL, "handle is NULL"); }
+int rfim_field_kind(const rfim_t *h) { return h ? h->kind : fail(RFIM_EINVAL, "handle is NULL"); }
+
+int rfim_temps(const rfim_t *h, double *T) {
+    if (!h || !T) return fail(RFIM_EINVAL, "NULL argument");
+    std::copy(h->T.begin(), h->T.end(), T);
+    return RFIM_OK;
+}
+
+int rfim_components(rfim_t *h, int64_t *B, double *F, int64_t *M) {
+    if (!h || !B || !F || !M) return fail(RFIM_EINVAL, "NULL argument");
+    int rc = compute_components(h);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(B, h->d_B, h->R * 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(F, h->d_F, h->R * 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(M, h->d_M, h->R * 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return RFIM_OK;
+}
+
+int rfim_energies(rfim_t *h, double *E) {
+    if (!h || !E) return fail(RFIM_EINVAL, "NULL argument");
+    int rc = compute_components(h);
+    if (rc) return rc;
+    std::vector<double> byrep(h->R);
+    HIPCHK(hipMemcpyAsync(byrep.data(), h->d_E, h->R * 8, hipMemcpyDeviceToHost, h->stream));
+    std::vector<int32_t> t2r;
+    if ((rc = download_perm(h, t2r))) return rc;
+    for (int t = 0; t < h->R; ++t) E[t] = byrep[t2r[t]];
+    return RFIM_OK;
+}
+
+int rfim_magnetizations(rfim_t *h, int64_t *M) {
+    if (!h || !M) return fail(RFIM_EINVAL, "NULL argument");
+    int rc = compute_components(h);
+    if (rc) return rc;
+    std::vector<int64_t> byrep(h->R);
+    HIPCHK(hipMemcpyAsync(byrep.data(), h->d_M, h->R * 8, hipMemcpyDeviceToHost, h->stream));
+    std::vector<int32_t> t2r;
+    if ((rc = download_perm(h, t2r))) return rc;
+    for (int t = 0; t < h->R; ++t) M[t] = byrep[t2r[t]];
+    return RFIM_OK;
+}
+
+int rfim_get_spins(rfim_t *h, int8_t *s) {
+    if (!h || !s) return fail(RFIM_EINVAL, "NULL argument");
+    const size_t N = (size_t)h->N, half = N / 2;
+    std::vector<uint8_t> dev((size_t)h->R * N);
+    HIPCHK(hipMemcpyAsync(dev.data(), h->d_spins, dev.size(), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (int r = 0; r < h->R; ++r) {
+        const uint8_t *src = dev.data() + (size_t)r * N;
+        int8_t *dst = s + (size_t)r * N;
+        for_each_site(h->L, [&](size_t i, int c, size_t j) { dst[i] = src[c * half + j] ? 1 : -1; });
+    }
+    return RFIM_OK;
+}
+
+int rfim_set_spins(rfim_t *h, const int8_t *s) {
+    if (!h || !s) return fail(RFIM_EINVAL, "NULL argument");
+    const size_t N = (size_t)h->N, half = N / 2;
+    for (size_t q = 0; q < (size_t)h->R * N; ++q)
+        if (s[q] != 1 && s[q] != -1) return fail(RFIM_EINVAL, "spins must be +-1 (index %zu)", q);
+    std::vector<uint8_t> dev((size_t)h->R * N);
+    for (int r = 0; r < h->R; ++r) {
+        uint8_t *dst = dev.data() + (size_t)r * N;
+        const int8_t *src = s + (size_t)r * N;
+        for_each_site(h->L, [&](size_t i, int c, size_t j) { dst[c * half + j] = src[i] > 0 ? 1 : 0; });
+    }
+    HIPCHK(hipMemcpyAsync(h->d_spins, dev.data(), dev.size(), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return RFIM_OK;
+}
+
+int rfim_get_perm(rfim_t *h, int32_t *t2r) {
+    if (!h || !t2r) return fail(RFIM_EINVAL, "NULL argument");
+    std::vector<int32_t> v;
+    int rc = download_perm(h, v);
+    if (rc) return rc;
+    std::copy(v.begin(), v.end(), t2r);
+    return RFIM_OK;
+}
+
+int rfim_set_perm(rfim_t *h, const int32_t *t2r) {
+    if (!h || !t2r) return fail(RFIM_EINVAL, "NULL argument");
+    std::vector<char> seen(h->R, 0);
+    for (int t = 0; t < h->R; ++t) {
+        if (t2r[t] < 0 || t2r[t] >= h->R || seen[t2r[t]]) return fail(RFIM_EINVAL, "t2r is not a permutation");
+        seen[t2r[t]] = 1;
+    }
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return upload_perm(h, std::vector<int32_t>(t2r, t2r + h->R));
+}
+
+int rfim_get_counters(rfim_t *h, uint64_t *t, uint64_t *k) {
+    if (!h || !t || !k) return fail(RFIM_EINVAL, "NULL argument");
+    uint64_t c[2];
+    HIPCHK(hipMemcpyAsync(c, h->d_ctrs, sizeof c, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (c[0] != h->t || c[1] != h->k) return fail(RFIM_EDEVICE, "device counters out of step");
+    *t = c[0];
+    *k = c[1];
+    return RFIM_OK;
+}
+
+int rfim_set_counters(rfim_t *h, uint64_t t, uint64_t k) {
+    if (!h) return fail(RFIM_EINVAL, "handle is NULL");
+    if (t > kMaxSweeps || k > 0xFFFFFFFFull) return fail(RFIM_ECAP, "counter beyond its range");
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->t = t;
+    h->k = k;
+    return upload_counters(h);
+}
+
+int rfim_exchange_stats(rfim_t *h, uint64_t *att, uint64_t *acc) {
+    if (!h || (h->R > 1 && (!att || !acc))) return fail(RFIM_EINVAL, "NULL argument");
+    if (h->R < 2) return RFIM_OK;
+    HIPCHK(hipMemcpyAsync(att, h->d_att, (h->R - 1) * 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(acc, h->d_acc, (h->R - 1) * 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return RFIM_OK;
+}
+
+int rfim_reset_exchange_stats(rfim_t *h) {
+    if (!h) return fail(RFIM_EINVAL, "handle is NULL");
+    return reset_stats(h);
+}
+
+int rfim_adapt_temps(rfim_t *h, int trials, int64_t sweeps_per_trial, int exchange_every,
+                     double rate_threshold, int max_insert_per_trial, int R_cap) {
+    if (!h) return fail(RFIM_EINVAL, "handle is NULL");
+    if (trials < 0 || sweeps_per_trial < 0 || exchange_every <= 0 || max_insert_per_trial < 0 ||
+        std::isnan(rate_threshold))
+        return fail(RFIM_EINVAL, "bad adapt arguments");
+    if (R_cap > h->R_cap) return fail(RFIM_ECAP, "R_cap %d beyond the capacity %d given at create", R_cap, h->R_cap);
+    if (h->t + (uint64_t)trials * (uint64_t)sweeps_per_trial > kMaxSweeps)
+        return fail(RFIM_ECAP, "global sweep counter would pass 2^31-1");
+    int rc;
+    for (int trial = 0; trial < trials; ++trial) {
+        // 1. trial run, continuing the chain, with fresh exchange counters
+        if ((rc = reset_stats(h))) return rc;
+        if ((rc = sweep_impl(h, sweeps_per_trial, exchange_every))) return rc;
+        const int R0 = h->R;
+        std::vector<uint64_t> att(R0), acc(R0);
+        HIPCHK(hipMemcpyAsync(att.data(), h->d_att, R0 * 8, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(acc.data(), h->d_acc, R0 * 8, hipMemcpyDeviceToHost, h->stream));
+        std::vector<int32_t> t2r;
+        if ((rc = download_perm(h, t2r))) return rc;
+        // 2-4. rates into a min-heap; pop the lowest below the threshold
+        using Item = std::pair<double, int>;
+        std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
+        for (int p = 0; p + 1 < R0; ++p)
+            if (att[p] > 0) heap.push({(double)acc[p] / (double)att[p], p});
+        std::vector<int> picked;
+        while (!heap.empty() && (int)picked.size() < max_insert_per_trial &&
+               R0 + (int)picked.size() < R_cap) {
+            Item it = heap.top();
+            heap.pop();
+            if (!(it.first < rate_threshold)) break;
+            picked.push_back(it.second);
+        }
+        if (picked.empty()) {
+            if ((rc = reset_stats(h))) return rc;
+            continue;
+        }
+        // 5-6. midpoint temperatures; new replica ids copy the colder end
+        std::vector<std::pair<double, int32_t>> slots;
+        for (int t = 0; t < R0; ++t) slots.push_back({h->T[t], t2r[t]});
+        for (size_t q = 0; q < picked.size(); ++q) {
+            const int p = picked[q];
+            const int32_t id = R0 + (int32_t)q;
+            slots.push_back({(h->T[p] + h->T[p + 1]) / 2.0, id});
+            HIPCHK(hipMemcpyAsync(h->d_spins + (size_t)id * h->N, h->d_spins + (size_t)t2r[p] * h->N,
+                                  (size_t)h->N, hipMemcpyDeviceToDevice, h->stream));
+        }
+        // 7. re-sort slots by temperature, rebuild permutation and tables
+        std::sort(slots.begin(), slots.end(),
+                  [](const std::pair<double, int32_t> &a, const std::pair<double, int32_t> &b) {
+                      return a.first < b.first;
+                  });
+        h->R = (int)slots.size();
+        h->T.resize(h->R);
+        std::vector<int32_t> nt2r(h->R);
+        for (int t = 0; t < h->R; ++t) {
+            h->T[t] = slots[t].first;
+            nt2r[t] = slots[t].second;
+        }
+        if ((rc = upload_perm(h, nt2r))) return rc;
+        if ((rc = upload_tables(h))) return rc;
+        if ((rc = reset_stats(h))) return rc;
+    }
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return h->R;
+}
+
+// ---- checkpoint ----------------------------------------------------
+// Blob: magic, version, L, R, R_cap, kind, J, h, seed, realization, t, k,
+// T[R], fields[N], spins[R][N] (+-1, natural order), t2r[R], att[R], acc[R].
+namespace {
+constexpr uint64_t kMagic = 0x314D494652ull;  // "RFIM1"
+struct Header {
+    uint64_t magic, version;
+    int32_t L, R, R_cap, kind;
+    double J, h;
+    uint64_t seed;
+    uint32_t rho, pad;
+    uint64_t t, k;
+};
+size_t blob_size(int L, int R) {
+    const size_t N = (size_t)L * L * L;
+    return sizeof(Header) + R * 8 + N * 4 + (size_t)R * N + R * 4 + 2 * (size_t)R * 8;
+}
+}  // namespace
+
+int rfim_save(rfim_t *h, void *buf, size_t *len) {
+    if (!h || !len) return fail(RFIM_EINVAL, "NULL argument");
+    const size_t need = blob_size(h->L, h->R);
+    if (!buf) {
+        *len = need;
+        return RFIM_OK;
+    }
+    if (*len < need) return fail(RFIM_EINVAL, "buffer too small (%zu < %zu)", *len, need);
+    uint8_t *p = (uint8_t *)buf;
+    Header hd;
+    std::memset(&hd, 0, sizeof hd);
+    hd.magic = kMagic;
+    hd.version = 1;
+    hd.L = h->L;
+    hd.R = h->R;
+    hd.R_cap = h->R_cap;
+    hd.kind = h->kind;
+    hd.J = h->J;
+    hd.h = h->h;
+    hd.seed = h->seed;
+    hd.rho = h->rho;
+    int rc = rfim_get_counters(h, &hd.t, &hd.k);
+    if (rc) return rc;
+    std::memcpy(p, &hd, sizeof hd);
+    p += sizeof hd;
+    std::memcpy(p, h->T.data(), h->R * 8);
+    p += h->R * 8;
+    std::memcpy(p, h->fields.data(), (size_t)h->N * 4);
+    p += (size_t)h->N * 4;
+    if ((rc = rfim_get_spins(h, (int8_t *)p))) return rc;
+    p += (size_t)h->R * h->N;
+    if ((rc = rfim_get_perm(h, (int32_t *)p))) return rc;
+    p += h->R * 4;
+    HIPCHK(hipMemcpyAsync(p, h->d_att, h->R * 8, hipMemcpyDeviceToHost, h->stream));
+    p += h->R * 8;
+    HIPCHK(hipMemcpyAsync(p, h->d_acc, h->R * 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    *len = need;
+    return RFIM_OK;
+}
+
+rfim_t *rfim_load(const void *buf, size_t len, void *hip_stream) {
+    if (!buf || len < sizeof(Header)) {
+        fail(RFIM_EINVAL, "checkpoint buffer too small");
+        return nullptr;
+    }
+    Header hd;
+    std::memcpy(&hd, buf, sizeof hd);
+    if (hd.magic != kMagic || hd.version != 1) {
+        fail(RFIM_EINVAL, "not an rfim checkpoint");
+        return nullptr;
+    }
+    if (hd.L < 2 || hd.L > 1024 || hd.R < 1 || hd.R > kMaxR || len < blob_size(hd.L, hd.R)) {
+        fail(RFIM_EINVAL, "corrupt checkpoint header");
+        return nullptr;
+    }
+    const uint8_t *p = (const uint8_t *)buf + sizeof hd;
+    const size_t N = (size_t)hd.L * hd.L * hd.L;
+    rfim_params_t prm;
+    std::memset(&prm, 0, sizeof prm);
+    prm.L = hd.L;
+    prm.R = hd.R;
+    prm.R_cap = hd.R_cap;
+    prm.J = hd.J;
+    prm.h = hd.h;
+    prm.seed = hd.seed;
+    prm.realization = hd.rho;
+    prm.field_kind = hd.kind;
+    std::vector<double> T(hd.R);
+    std::memcpy(T.data(), p, hd.R * 8);
+    p += hd.R * 8;
+    std::vector<float> f(N);
+    std::memcpy(f.data(), p, N * 4);
+    p += N * 4;
+    prm.temps = T.data();
+    prm.fields = f.data();
+    rfim *h = rfim_create_ex(&prm, hip_stream);
+    if (!h) return nullptr;
+    int rc = rfim_set_spins(h, (const int8_t *)p);
+    p += (size_t)hd.R * N;
+    if (!rc) {
+        std::vector<int32_t> t2r(hd.R);
+        std::memcpy(t2r.data(), p, hd.R * 4);
+        rc = rfim_set_perm(h, t2r.data());
+    }
+    p += hd.R * 4;
+    if (!rc) rc = rfim_set_counters(h, hd.t, hd.k);
+    if (!rc) {
+        hipError_t e1 = hipMemcpyAsync(h->d_att, p, hd.R * 8, hipMemcpyHostToDevice, h->stream);
+        hipError_t e2 = hipMemcpyAsync(h->d_acc, p + hd.R * 8, hd.R * 8, hipMemcpyHostToDevice, h->stream);
+        hipError_t e3 = hipStreamSynchronize(h->stream);
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) rc = fail(RFIM_EDEVICE, "checkpoint upload failed");
+    }
+    if (rc) {
+        std::string msg = g_error;
+        destroy_impl(h);
+        g_error = msg;
+        return nullptr;
+    }
+    return h;
+}
+
+}  // extern "C"

@@ -1,0 +1,293 @@
+"""Thin ctypes binding of librfim.so: the C ABI of include/rfim.h under the
+same names, plus a small ``Rfim`` handle class.  Argument marshalling only;
+every step of the method runs in the library's HIP kernels.
+
+PyTorch supplies the HIP runtime and streams: it is imported before the
+library is opened so that both share one runtime, and ``Rfim`` issues its
+work on a ``torch.cuda`` stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librfim.so")
+
+RFIM_OK, RFIM_EINVAL, RFIM_ENOMEM, RFIM_EDEVICE, RFIM_ESTATE, RFIM_ECAP, RFIM_EBUSY = 0, -1, -2, -3, -4, -5, -6
+FIELDS_AUTO, FIELDS_BIMODAL, FIELDS_CONTINUOUS = -1, 0, 1
+
+# Every symbol include/rfim.h declares (checked by the CPU tests).
+EXPORTS = [
+    "rfim_create", "rfim_create_ex", "rfim_sweep", "rfim_energies", "rfim_adapt_temps",
+    "rfim_destroy", "rfim_last_error", "rfim_set_stream", "rfim_synchronize",
+    "rfim_num_replicas", "rfim_lattice_size", "rfim_field_kind", "rfim_temps",
+    "rfim_magnetizations", "rfim_components", "rfim_get_spins", "rfim_set_spins",
+    "rfim_get_perm", "rfim_set_perm", "rfim_get_counters", "rfim_set_counters",
+    "rfim_exchange_stats", "rfim_reset_exchange_stats", "rfim_save", "rfim_load",
+]
+
+
+class RfimError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("rfim error %d: %s" % (code, msg))
+        self.code = code
+
+
+class rfim_params_t(C.Structure):
+    _fields_ = [("L", C.c_int), ("R", C.c_int), ("R_cap", C.c_int), ("J", C.c_double),
+                ("h", C.c_double), ("fields", C.c_void_p), ("temps", C.c_void_p),
+                ("seed", C.c_uint64), ("realization", C.c_uint32), ("field_kind", C.c_int)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Open librfim.so (after torch, so that one HIP runtime serves both).
+    Raises if the library has not been built: there is no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    try:
+        import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+    except Exception:
+        pass
+    if not os.path.exists(path):
+        raise RuntimeError("librfim.so not built: run python -m paper_1508_06268_amd.build")
+    L = C.CDLL(path)
+    vp, i32, i64, u64, dbl, sz = C.c_void_p, C.c_int, C.c_int64, C.c_uint64, C.c_double, C.c_size_t
+    sig = {
+        "rfim_create": (vp, [i32, i32, dbl, dbl, vp, vp, u64]),
+        "rfim_create_ex": (vp, [C.POINTER(rfim_params_t), vp]),
+        "rfim_sweep": (i32, [vp, i64, i32]),
+        "rfim_energies": (i32, [vp, vp]),
+        "rfim_adapt_temps": (i32, [vp, i32, i64, i32, dbl, i32, i32]),
+        "rfim_destroy": (None, [vp]),
+        "rfim_last_error": (C.c_char_p, []),
+        "rfim_set_stream": (i32, [vp, vp]),
+        "rfim_synchronize": (i32, [vp]),
+        "rfim_num_replicas": (i32, [vp]),
+        "rfim_lattice_size": (i32, [vp]),
+        "rfim_field_kind": (i32, [vp]),
+        "rfim_temps": (i32, [vp, vp]),
+        "rfim_magnetizations": (i32, [vp, vp]),
+        "rfim_components": (i32, [vp, vp, vp, vp]),
+        "rfim_get_spins": (i32, [vp, vp]),
+        "rfim_set_spins": (i32, [vp, vp]),
+        "rfim_get_perm": (i32, [vp, vp]),
+        "rfim_set_perm": (i32, [vp, vp]),
+        "rfim_get_counters": (i32, [vp, vp, vp]),
+        "rfim_set_counters": (i32, [vp, u64, u64]),
+        "rfim_exchange_stats": (i32, [vp, vp, vp]),
+        "rfim_reset_exchange_stats": (i32, [vp]),
+        "rfim_save": (i32, [vp, vp, C.POINTER(sz)]),
+        "rfim_load": (vp, [vp, sz, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return load_library().rfim_last_error().decode()
+
+
+def _check(rc):
+    if rc < 0:
+        raise RfimError(rc, last_error())
+    return rc
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+# ---- C ABI under the same names ---------------------------------------
+def rfim_create(L, R, J, h, fields, temps, seed):
+    f = np.ascontiguousarray(fields, dtype=np.float32).reshape(-1)
+    T = np.ascontiguousarray(temps, dtype=np.float64).reshape(-1)
+    return load_library().rfim_create(int(L), int(R), float(J), float(h), _p(f), _p(T),
+                                      int(seed) & 0xFFFFFFFFFFFFFFFF)
+
+
+def rfim_create_ex(L, R, J, h, fields, temps, seed=0, realization=0, field_kind=FIELDS_AUTO,
+                   R_cap=0, stream=None):
+    f = np.ascontiguousarray(fields, dtype=np.float32).reshape(-1)
+    T = np.ascontiguousarray(temps, dtype=np.float64).reshape(-1)
+    if f.size != int(L) ** 3 or T.size != int(R):
+        raise ValueError("fields must hold L^3 values and temps R values")
+    prm = rfim_params_t(int(L), int(R), int(R_cap), float(J), float(h), f.ctypes.data,
+                        T.ctypes.data, int(seed) & 0xFFFFFFFFFFFFFFFF, int(realization),
+                        int(field_kind))
+    return load_library().rfim_create_ex(C.byref(prm), stream)
+
+
+def rfim_sweep(handle, n, exchange_every):
+    return _check(load_library().rfim_sweep(handle, int(n), int(exchange_every)))
+
+
+def rfim_energies(handle, R):
+    E = np.zeros(R, dtype=np.float64)
+    _check(load_library().rfim_energies(handle, _p(E)))
+    return E
+
+
+def rfim_adapt_temps(handle, trials, sweeps_per_trial, exchange_every, rate_threshold,
+                     max_insert_per_trial, R_cap):
+    return _check(load_library().rfim_adapt_temps(handle, int(trials), int(sweeps_per_trial),
+                                                  int(exchange_every), float(rate_threshold),
+                                                  int(max_insert_per_trial), int(R_cap)))
+
+
+def rfim_destroy(handle):
+    load_library().rfim_destroy(handle)
+
+
+class Rfim:
+    """One disorder realization on the GPU (owns a librfim handle)."""
+
+    def __init__(self, L, R, J, h, fields, temps, seed=0, realization=0, field_kind=FIELDS_AUTO,
+                 R_cap=0, stream=None):
+        self.L = int(L)
+        self.N = self.L ** 3
+        self._torch_stream = None
+        sptr = None
+        if stream is not None:
+            self._torch_stream = stream
+            sptr = C.c_void_p(int(stream.cuda_stream))
+        self._h = rfim_create_ex(L, R, J, h, fields, temps, seed, realization, field_kind, R_cap,
+                                 sptr)
+        if not self._h:
+            raise ValueError(last_error())
+
+    @classmethod
+    def _wrap(cls, handle, L):
+        obj = cls.__new__(cls)
+        obj.L = int(L)
+        obj.N = obj.L ** 3
+        obj._torch_stream = None
+        obj._h = handle
+        return obj
+
+    def close(self):
+        if getattr(self, "_h", None):
+            rfim_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def R(self) -> int:
+        return load_library().rfim_num_replicas(self._h)
+
+    @property
+    def field_kind(self) -> int:
+        return load_library().rfim_field_kind(self._h)
+
+    def set_stream(self, stream):
+        """Issue future work on a torch.cuda.Stream (None: the handle's own)."""
+        self._torch_stream = stream
+        ptr = C.c_void_p(int(stream.cuda_stream)) if stream is not None else None
+        _check(load_library().rfim_set_stream(self._h, ptr))
+
+    def synchronize(self):
+        _check(load_library().rfim_synchronize(self._h))
+
+    def sweep(self, n, every=0):
+        rfim_sweep(self._h, n, every)
+
+    def energies(self) -> np.ndarray:
+        return rfim_energies(self._h, self.R)
+
+    def magnetizations(self) -> np.ndarray:
+        M = np.zeros(self.R, dtype=np.int64)
+        _check(load_library().rfim_magnetizations(self._h, _p(M)))
+        return M
+
+    def components(self):
+        R = self.R
+        B = np.zeros(R, dtype=np.int64)
+        F = np.zeros(R, dtype=np.float64)
+        M = np.zeros(R, dtype=np.int64)
+        _check(load_library().rfim_components(self._h, _p(B), _p(F), _p(M)))
+        return B, F, M
+
+    def temps(self) -> np.ndarray:
+        T = np.zeros(self.R, dtype=np.float64)
+        _check(load_library().rfim_temps(self._h, _p(T)))
+        return T
+
+    def spins(self) -> np.ndarray:
+        s = np.zeros((self.R, self.N), dtype=np.int8)
+        _check(load_library().rfim_get_spins(self._h, _p(s)))
+        return s
+
+    def set_spins(self, s):
+        a = np.ascontiguousarray(s, dtype=np.int8).reshape(self.R, self.N)
+        _check(load_library().rfim_set_spins(self._h, _p(a)))
+
+    def perm(self) -> np.ndarray:
+        p = np.zeros(self.R, dtype=np.int32)
+        _check(load_library().rfim_get_perm(self._h, _p(p)))
+        return p
+
+    def set_perm(self, t2r):
+        a = np.ascontiguousarray(t2r, dtype=np.int32)
+        _check(load_library().rfim_set_perm(self._h, _p(a)))
+
+    def counters(self):
+        t = C.c_uint64()
+        k = C.c_uint64()
+        _check(load_library().rfim_get_counters(self._h, C.byref(t), C.byref(k)))
+        return t.value, k.value
+
+    def set_counters(self, t, k):
+        _check(load_library().rfim_set_counters(self._h, int(t), int(k)))
+
+    def exchange_stats(self):
+        n = max(self.R - 1, 0)
+        att = np.zeros(max(n, 1), dtype=np.uint64)
+        acc = np.zeros(max(n, 1), dtype=np.uint64)
+        _check(load_library().rfim_exchange_stats(self._h, _p(att), _p(acc)))
+        return att[:n], acc[:n]
+
+    def reset_exchange_stats(self):
+        _check(load_library().rfim_reset_exchange_stats(self._h))
+
+    def adapt_temps(self, trials, sweeps_per_trial, every, rate_threshold, max_insert_per_trial,
+                    R_cap):
+        return rfim_adapt_temps(self._h, trials, sweeps_per_trial, every, rate_threshold,
+                                max_insert_per_trial, R_cap)
+
+    def save(self) -> bytes:
+        n = C.c_size_t(0)
+        _check(load_library().rfim_save(self._h, None, C.byref(n)))
+        buf = (C.c_uint8 * n.value)()
+        _check(load_library().rfim_save(self._h, buf, C.byref(n)))
+        return bytes(buf)
+
+    @classmethod
+    def load(cls, blob: bytes, stream=None):
+        buf = (C.c_uint8 * len(blob)).from_buffer_copy(blob)
+        sptr = C.c_void_p(int(stream.cuda_stream)) if stream is not None else None
+        h = load_library().rfim_load(buf, len(blob), sptr)
+        if not h:
+            raise ValueError(last_error())
+        L = load_library().rfim_lattice_size(h)
+        obj = cls._wrap(h, L)
+        obj._torch_stream = stream
+        return obj

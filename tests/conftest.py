@@ -18,3 +18,19 @@ def oracle_mod():
     from oracle import oracle
     oracle.build()
     return oracle
+
+
+@pytest.fixture(autouse=True)
+def _announce_gpu_case(request):
+    # Name the case before any GPU work so that a run that loses the box
+    # still says which test it was in.
+    if request.node.get_closest_marker("gpu") is not None:
+        print("\n[gpu case] %s" % request.node.nodeid, flush=True)
+    yield
+
+
+@pytest.fixture(scope="session")
+def rfim_mod():
+    import paper_1508_06268_amd as P
+    P.load_library()
+    return P

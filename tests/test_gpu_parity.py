@@ -1,0 +1,112 @@
+"""HIP path vs CPU oracle, element by element, on the same seeded inputs.
++-1 fields: the whole chain (spins, permutation, counters, exchange
+statistics, energies, magnetisations) must match bit for bit."""
+import numpy as np
+import pytest
+
+from paper_1508_06268_amd import workloads as W
+from parity_util import assert_same_state, make_pair
+
+pytestmark = pytest.mark.gpu
+
+
+def test_plain_l8_full_run(rfim_mod, oracle_mod):
+    w = W.plain_l8()
+    g, o = make_pair(rfim_mod, oracle_mod, w.L, w.R, w.J, w.h, w.fields, w.temps, seed=w.seed)
+    assert_same_state(g, o, "initial")
+    g.sweep(w.sweeps, w.every)
+    o.sweep(w.sweeps, w.every)
+    assert_same_state(g, o, "after 1000 sweeps")
+
+
+@pytest.mark.parametrize("L,R,h,sweeps,every", [
+    (2, 4, 1.0, 300, 3),       # smallest lattice: +-x neighbours coincide
+    (4, 5, 1.5, 200, 7),       # generic kernel
+    (6, 3, 2.0, 100, 5),       # generic kernel, dE = 0 ties
+    (10, 4, 1.0, 30, 10),      # generic kernel, rows not a multiple of 4 groups
+    (16, 8, 2.25, 60, 10),     # power-of-two kernel, several workgroups per replica
+    (32, 6, 1.0, 20, 10),
+])
+def test_bimodal_sizes(rfim_mod, oracle_mod, L, R, h, sweeps, every):
+    f = W.bimodal_fields(L, [11, L])
+    T = W.linear_temps(R, 1.0, 6.0)
+    g, o = make_pair(rfim_mod, oracle_mod, L, R, 1.0, h, f, T, seed=1234567890123 + L, realization=L)
+    g.sweep(sweeps, every)
+    o.sweep(sweeps, every)
+    assert_same_state(g, o, "L=%d" % L)
+
+
+def test_split_calls_and_ragged_intervals(rfim_mod, oracle_mod):
+    L, R = 8, 6
+    f = W.bimodal_fields(L, [12, 0])
+    T = W.geometric_temps(R, 1.0, 6.0)
+    g, o = make_pair(rfim_mod, oracle_mod, L, R, 1.0, 1.0, f, T, seed=5)
+    for n, every in ((3, 10), (7, 10), (25, 10), (1, 0), (9, 4), (0, 3)):
+        g.sweep(n, every)
+        o.sweep(n, every)
+    assert_same_state(g, o, "split")
+
+
+def test_state_injection_at_paper_scale(rfim_mod, oracle_mod):
+    """L=64 with 128 replicas, in the launch configuration of the benchmark:
+    start both from the same random state and permutation mid-run and
+    compare after one exchange interval."""
+    L, R = 64, 128
+    f = W.bimodal_fields(L, [0, 2])
+    T = W.linear_temps(R, 1.0, 6.0)
+    g, o = make_pair(rfim_mod, oracle_mod, L, R, 1.0, 2.25, f, T, seed=0, R_cap=192)
+    s = W.random_spins(R, L, [3, 3])
+    perm = np.random.default_rng(4).permutation(R).astype(np.int32)
+    for x in (g, o):
+        x.set_spins(s)
+        x.set_perm(perm)
+        x.set_counters(12340, 1234)
+    g.sweep(10, 10)
+    o.sweep(10, 10)
+    assert_same_state(g, o, "L=64 injected")
+
+
+def test_adapt_matches_oracle(rfim_mod, oracle_mod):
+    L, R = 8, 8
+    f = W.bimodal_fields(L, [13, 0])
+    T = W.linear_temps(R, 1.0, 6.0)
+    g, o = make_pair(rfim_mod, oracle_mod, L, R, 1.0, 1.0, f, T, seed=77, R_cap=14)
+    rg = g.adapt_temps(3, 200, 10, 0.6, 2, 14)
+    ro = o.adapt_temps(3, 200, 10, 0.6, 2, 14)
+    assert rg == ro and rg > R
+    assert_same_state(g, o, "after adapt")
+    g.sweep(100, 10)
+    o.sweep(100, 10)
+    assert_same_state(g, o, "after adapt + run")
+
+
+def test_checkpoint_resume_bit_exact(rfim_mod, oracle_mod):
+    L, R = 16, 6
+    f = W.bimodal_fields(L, [14, 0])
+    T = W.linear_temps(R, 1.5, 5.0)
+    a = rfim_mod.Rfim(L, R, 1.0, 1.0, f, T, seed=3)
+    a.sweep(100, 10)
+    b = rfim_mod.Rfim(L, R, 1.0, 1.0, f, T, seed=3)
+    b.sweep(47, 10)
+    blob = b.save()
+    b.close()
+    c = rfim_mod.Rfim.load(blob)
+    c.sweep(53, 10)
+    assert np.array_equal(a.spins(), c.spins())
+    assert np.array_equal(a.perm(), c.perm())
+    assert a.counters() == c.counters()
+
+
+def test_repeat_runs_identical(rfim_mod):
+    L, R = 32, 8
+    f = W.gaussian_fields(L, [15, 0])
+    T = W.geometric_temps(R, 1.0, 6.0)
+    runs = []
+    for _ in range(2):
+        g = rfim_mod.Rfim(L, R, 1.0, 2.0, f, T, seed=9)
+        g.sweep(50, 10)
+        runs.append((g.spins(), g.perm(), g.energies()))
+        g.close()
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert np.array_equal(runs[0][1], runs[1][1])
+    assert np.array_equal(runs[0][2], runs[1][2])
