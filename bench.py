@@ -1,0 +1,195 @@
+"""Benchmark: Exchange Monte Carlo for the 3D RFIM on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload adaptive_l64]
+
+One step is one whole disorder realization of the named workload run through
+the hot path: checkerboard Metropolis sweeps over all replicas, the
+per-replica energy reduction and the replica exchange every 10 sweeps, with
+the adaptive temperature trials in front (Sec. 3.1, 3.3, 4).  The default
+workload is L=64 with bimodal fields h=2.25, 128 replicas linear in T [1, 6],
+4 trial runs of 2000 sweeps inserting temperatures where the adjacent rate
+is below 0.2 (cap 192, at most 16 per trial), then 2x10^4 sweeps.
+
+Inputs (fields, temperatures, the realization's handle) are resident on
+the GPU before the timed region.  Prints one JSON line on stdout; progress
+goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "spin-flip attempts/ns & % HBM roofline at L=64; realizations/s + p99 latency"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1508_06268_amd", "csrc", "rfim_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_pow2_l64_r192_traffic.txt")
+# Algorithmic HBM bytes per spin-flip attempt of one half-sweep with one-byte
+# spins: read the site (1), read the other colour once (1), read the field
+# (1 for +-1 fields, 4 for FP32 fields), write the site (1).
+BYTES_PER_ATTEMPT = {0: 4.0, 1: 7.0}
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(bytes_algo_per_launch):
+    """HBM bytes per launch of the sweep kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    text = open(TRAFFIC_FILE).read()
+    m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
+    m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+def run_realization(h, w, stream, torch):
+    """One realization: adaptive trials then the production sweeps.
+    Returns the number of spin-flip attempts issued."""
+    N = w.L ** 3
+    attempts = 0
+    a = w.adapt
+    for _ in range(a["trials"]):
+        attempts += h.R * N * a["sweeps_per_trial"]
+        h.adapt_temps(1, a["sweeps_per_trial"], a["every"], a["rate_threshold"],
+                      a["max_insert_per_trial"], a["R_cap"])
+    attempts += h.R * N * w.sweeps
+    h.sweep(w.sweeps, w.every)
+    return attempts
+
+
+def cpu_baseline(w, sweeps=20):
+    """The CPU oracle on a bounded sample of the same workload: the initial
+    replica set for `sweeps` sweeps with exchange every 10."""
+    from oracle import oracle as O
+
+    O.build()
+    o = O.Oracle(w.L, w.R, w.J, w.h, w.fields, w.temps, seed=w.seed)
+    t0 = time.perf_counter()
+    o.sweep(sweeps, w.every)
+    dt = time.perf_counter() - t0
+    att = w.R * w.L ** 3 * sweeps
+    return {"value": att / (dt * 1e9), "unit": "spin-flip attempts/ns", "cores": 1, "kind": "oracle",
+            "sample": "L=%d, R=%d, %d sweeps with exchange every %d (%.2e attempts, %.1f s, 1 thread)"
+                      % (w.L, w.R, sweeps, w.every, att, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="adaptive_l64", choices=["adaptive_l64"])
+    ap.add_argument("--production-sweeps", type=int, default=20000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs a realization on a single MI355X "
+              "(multi-GPU sharding is described in DESIGN.md, not built); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1508_06268_amd as P
+    from paper_1508_06268_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    w = W.adaptive_l64(sweeps=args.production_sweeps)
+    stream = torch.cuda.Stream()
+    log("creating %d handles: L=%d R=%d R_cap=%d" % (args.warmup + args.steps, w.L, w.R, w.R_cap))
+    handles = [P.Rfim(w.L, w.R, w.J, w.h, w.fields, w.temps, seed=w.seed, R_cap=w.R_cap, stream=stream)
+               for _ in range(args.warmup + args.steps)]
+    torch.cuda.synchronize()
+
+    for q in range(args.warmup):
+        t0 = time.perf_counter()
+        run_realization(handles[q], w, stream, torch)
+        handles[q].synchronize()
+        log("warmup %d: %.3f s, R=%d" % (q, time.perf_counter() - t0, handles[q].R))
+
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    attempts = 0
+    ev0.record(stream)
+    t0 = time.perf_counter()
+    for q in range(args.steps):
+        h = handles[args.warmup + q]
+        attempts += run_realization(h, w, stream, torch)
+        log("step %d issued, R=%d" % (q, h.R))
+    ev1.record(stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    elapsed_s = max(wall, gpu_ms / 1e3)
+    value = attempts / (elapsed_s * 1e9)
+    R_final = handles[-1].R
+    log("timed: %d steps, %.2e attempts, %.3f s wall, %.3f s events -> %.1f attempts/ns"
+        % (args.steps, attempts, wall, gpu_ms / 1e3, value))
+
+    # Roofline leg: the dominant kernel (one half-sweep of every replica) at
+    # the production shape, timed with events on the handle's stream.
+    h = handles[-1]
+    n_roof = 200
+    h.sweep(10, 0)
+    stream.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    h.sweep(n_roof, 0)
+    e1.record(stream)
+    stream.synchronize()
+    launch_us = e0.elapsed_time(e1) * 1e3 / (2 * n_roof)
+    kind = h.field_kind
+    attempts_per_launch = R_final * w.L ** 3 // 2
+    bytes_per_launch = BYTES_PER_ATTEMPT[kind] * attempts_per_launch
+    achieved = bytes_per_launch / (launch_us * 1e-6) / 1e9
+    traffic = measured_traffic(bytes_per_launch)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "sweep_pow2<bimodal>", "launch_us": round(launch_us, 3),
+                "bytes_per_launch": bytes_per_launch, "attempts_per_ns_kernel":
+                    round(attempts_per_launch / (launch_us * 1e3), 1)}
+    log("roofline: %.2f us per half-sweep launch, %.0f GB/s algorithmic" % (launch_us, achieved))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on a bounded sample")
+        cpu = cpu_baseline(w)
+
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "spin-flip attempts/ns", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(elapsed_s * 1e3 / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "adaptive_l64", "L": w.L, "R0": w.R, "R_final": R_final,
+                   "fields": "bimodal +-1", "J": w.J, "h": w.h, "T": [1.0, 6.0],
+                   "trial_runs": w.adapt["trials"], "trial_sweeps": w.adapt["sweeps_per_trial"],
+                   "rate_threshold": w.adapt["rate_threshold"], "R_cap": w.R_cap,
+                   "production_sweeps": w.sweeps, "exchange_every": w.every,
+                   "attempts_per_step": attempts // args.steps},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

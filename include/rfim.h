@@ -161,6 +161,16 @@ int rfim_set_counters(rfim_t *h, uint64_t t, uint64_t k);
 int rfim_exchange_stats(rfim_t *h, uint64_t *att, uint64_t *acc);
 int rfim_reset_exchange_stats(rfim_t *h);
 
+/* Launch shape of the sweep kernels (no effect on results: every shape
+ * gives bit-identical chains).  For L = 2^l >= 8: mode 0 streams every
+ * half-sweep through HBM with nw in {1, 2, 4} dwords (4 sites each) per
+ * thread and wg in {64, 128, 256} threads per workgroup; mode 1 (L <= 32)
+ * keeps each replica in one workgroup's LDS (wg in {64, ..., 1024}) for all
+ * sweeps of an exchange interval.  Other L have the single shape (0, 0, 0).
+ * RFIM_EINVAL for a shape not valid for the handle's L. */
+int rfim_set_launch_shape(rfim_t *h, int mode, int nw, int wg);
+int rfim_get_launch_shape(const rfim_t *h, int *mode, int *nw, int *wg);
+
 /* Checkpoint: the whole chain state (parameters, fields, temperatures,
  * spins, permutation, counters, exchange statistics) as a byte blob.
  * rfim_save with buf == NULL stores the needed size in *len.  A handle

@@ -69,6 +69,7 @@ struct rfim {
     int64_t *d_B = nullptr, *d_M = nullptr;
     double *d_F = nullptr;
     int nblk = 1;
+    int mode = 0, nw = 0, wg = 0;   // launch shape (see rfim_set_launch_shape)
 
     Lattice lattice() const {
         Lattice a;
@@ -99,6 +100,9 @@ struct rfim {
         a.ctrs = d_ctrs;
         a.part = d_part;
         a.nblk = nblk;
+        a.mode = mode;
+        a.nw = nw;
+        a.wg = wg;
         a.E = d_E;
         return a;
     }
@@ -147,33 +151,38 @@ int validate(const rfim_params_t *p, int *kind_out) {
     return RFIM_OK;
 }
 
-// Metropolis thresholds for +-1 fields (class = 2k + fb, dE = 2(J a + h b),
-// a = 2k - 6, b = 2 fb - 1), FP64 on the host: floor(exp(-beta dE) 2^32)
-// clamped to 2^32 - 1; classes with dE <= 0 are always accepted.
-double class_delta(const rfim *h, int cls) {
-    const int a = 2 * (cls >> 1) - 6;
-    const int b = 2 * (cls & 1) - 1;
-    return 2.0 * (h->J * (double)a + h->h * (double)b);
+// Metropolis thresholds for +-1 fields.  The device indexes them by
+// idx = (up << 2) | (b << 1) | f: up = number of +1 neighbours (0..6),
+// b = 1 iff s_i = +1, f = 1 iff h_i = +1.  With s = 2b-1, the flip costs
+// dE = 2(J a + h c), a = s (2 up - 6) = s_i n_i, c = s (2f - 1) = s_i h_i.
+// FP64 on the host: thr = floor(exp(-beta dE) 2^32) clamped to 2^32 - 1;
+// entries with dE <= 0 are always accepted (marked in always_mask).
+double index_delta(const rfim *h, int idx) {
+    const int up = idx >> 2, b = (idx >> 1) & 1, f = idx & 1;
+    const int s = 2 * b - 1;
+    const int a = s * (2 * up - 6);
+    const int c = s * (2 * f - 1);
+    return 2.0 * (h->J * (double)a + h->h * (double)c);
 }
 
 int upload_tables(rfim *h) {
-    std::vector<uint32_t> thr((size_t)h->R * 16, 0u);
+    std::vector<uint32_t> thr((size_t)h->R * 32, 0u);
     std::vector<double> beta(h->R);
     std::vector<float> betaf(h->R);
     uint32_t mask = 0;
-    for (int c = 0; c < 14; ++c)
-        if (class_delta(h, c) <= 0.0) mask |= 1u << c;
+    for (int idx = 0; idx < 28; ++idx)
+        if (index_delta(h, idx) <= 0.0) mask |= 1u << idx;
     h->always_mask = mask;
     for (int t = 0; t < h->R; ++t) {
         beta[t] = 1.0 / h->T[t];
         betaf[t] = (float)beta[t];
-        for (int c = 0; c < 14; ++c) {
-            if (mask & (1u << c)) {
-                thr[(size_t)t * 16 + c] = 0xFFFFFFFFu;
+        for (int idx = 0; idx < 28; ++idx) {
+            if (mask & (1u << idx)) {
+                thr[(size_t)t * 32 + idx] = 0xFFFFFFFFu;
                 continue;
             }
-            const double scaled = std::ldexp(std::exp(-(beta[t] * class_delta(h, c))), 32);
-            thr[(size_t)t * 16 + c] = scaled >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)std::floor(scaled);
+            const double scaled = std::ldexp(std::exp(-(beta[t] * index_delta(h, idx))), 32);
+            thr[(size_t)t * 32 + idx] = scaled >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)std::floor(scaled);
         }
     }
     HIPCHK(hipMemcpyAsync(h->d_thr, thr.data(), thr.size() * 4, hipMemcpyHostToDevice, h->stream));
@@ -197,7 +206,15 @@ void for_each_site(int L, F f) {
 
 int alloc_device(rfim *h) {
     const size_t N = (size_t)h->N, half = N / 2, Rc = (size_t)h->R_cap;
-    h->nblk = rfim_dev::energy_blocks_per_replica(h->L);
+    // partials buffer sized for the shape with the most workgroups
+    int maxblk = 64;
+    if (h->log2L >= 3) {
+        for (int nw : {1, 2, 4})
+            for (int wg : {64, 128, 256})
+                if (rfim_dev::shape_valid(h->L, 0, nw, wg))
+                    maxblk = std::max(maxblk, rfim_dev::blocks_per_replica(h->L, 0, nw, wg));
+    }
+    h->nblk = rfim_dev::blocks_per_replica(h->L, h->mode, h->nw, h->wg);
 #define ALLOC(ptr, bytes)                                                                \
     do {                                                                                 \
         hipError_t e_ = hipMalloc((void **)&(ptr), (bytes));                             \
@@ -210,7 +227,7 @@ int alloc_device(rfim *h) {
         ALLOC(h->d_fhf, N * sizeof(float));
         ALLOC(h->d_fraw, N * sizeof(float));
     }
-    ALLOC(h->d_thr, Rc * 16 * sizeof(uint32_t));
+    ALLOC(h->d_thr, Rc * 32 * sizeof(uint32_t));
     ALLOC(h->d_betaf, Rc * sizeof(float));
     ALLOC(h->d_beta, Rc * sizeof(double));
     ALLOC(h->d_t2r, Rc * sizeof(int32_t));
@@ -218,7 +235,7 @@ int alloc_device(rfim *h) {
     ALLOC(h->d_att, Rc * sizeof(uint64_t));
     ALLOC(h->d_acc, Rc * sizeof(uint64_t));
     ALLOC(h->d_ctrs, 2 * sizeof(uint64_t));
-    ALLOC(h->d_part, Rc * (size_t)h->nblk * 3 * sizeof(double));
+    ALLOC(h->d_part, Rc * (size_t)maxblk * 3 * sizeof(double));
     ALLOC(h->d_E, Rc * sizeof(double));
     ALLOC(h->d_B, Rc * sizeof(int64_t));
     ALLOC(h->d_M, Rc * sizeof(int64_t));
@@ -232,7 +249,7 @@ int upload_fields(rfim *h) {
     const size_t N = (size_t)h->N, half = N / 2;
     if (h->kind == 0) {
         std::vector<uint8_t> fb(N);
-        for_each_site(h->L, [&](size_t i, int c, size_t j) { fb[c * half + j] = h->fields[i] > 0.0f ? 1 : 0; });
+        for_each_site(h->L, [&](size_t i, int c, size_t j) { fb[c * half + j] = h->fields[i] > 0.0f ? 4 : 0; });
         HIPCHK(hipMemcpyAsync(h->d_fbits, fb.data(), N, hipMemcpyHostToDevice, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
     } else {
@@ -284,6 +301,26 @@ int compute_components(rfim *h) {
     return RFIM_OK;
 }
 
+// Default launch shape: tiny lattices run LDS-resident (launch-bound
+// otherwise), larger ones stream with four dwords per thread.  The
+// autotuner in the Python package measures and overrides these.
+void default_shape(int L, int R, int *mode, int *nw, int *wg) {
+    if (!(L >= 8 && (L & (L - 1)) == 0)) {
+        *mode = 0; *nw = 0; *wg = 0;
+        return;
+    }
+    if (L <= 16) {
+        *mode = 1;
+        *nw = L == 8 ? 1 : 2;
+        *wg = L == 8 ? 64 : 256;
+        return;
+    }
+    *mode = 0;
+    *nw = L >= 64 ? 4 : 1;
+    *wg = 256;
+    (void)R;
+}
+
 rfim *create_impl(const rfim_params_t *p, void *stream, int *err) {
     int kind = 0;
     *err = validate(p, &kind);
@@ -309,6 +346,7 @@ rfim *create_impl(const rfim_params_t *p, void *stream, int *err) {
         while ((1 << l) < p->L) ++l;
         h->log2L = l;
     }
+    default_shape(h->L, h->R_cap, &h->mode, &h->nw, &h->wg);
     h->fields.assign(p->fields, p->fields + h->N);
     h->T.assign(p->temps, p->temps + p->R);
     if (stream) {
@@ -354,12 +392,18 @@ int sweep_impl(rfim *h, int64_t n, int every) {
     while (remaining > 0) {
         int64_t to_next = every > 0 ? (int64_t)(every - (int64_t)(h->t % (uint64_t)every)) : remaining;
         const int m = (int)std::min<int64_t>(remaining, to_next);
-        for (int q = 0; q < m; ++q) {
-            HIPCHK(rfim_dev::launch_sweep(lat, 0, q, h->stream));
-            HIPCHK(rfim_dev::launch_sweep(lat, 1, q, h->stream));
+        const bool exch = every > 0 && m == to_next;
+        const bool fused = exch && rfim_dev::fused_energy(lat);
+        if (h->mode == 1) {
+            HIPCHK(rfim_dev::launch_resident(lat, m, fused ? 1 : 0, h->stream));
+        } else {
+            for (int q = 0; q < m; ++q) {
+                HIPCHK(rfim_dev::launch_sweep(lat, 0, q, 0, h->stream));
+                HIPCHK(rfim_dev::launch_sweep(lat, 1, q, fused && q == m - 1, h->stream));
+            }
         }
-        if (every > 0 && m == to_next) {
-            HIPCHK(rfim_dev::launch_energy(lat, h->stream));
+        if (exch) {
+            if (!fused) HIPCHK(rfim_dev::launch_energy(lat, h->stream));
             HIPCHK(rfim_dev::launch_exchange(lat, m, h->stream));
             h->k += 1;
         } else {
@@ -635,6 +679,26 @@ int rfim_adapt_temps(rfim_t *h, int trials, int64_t sweeps_per_trial, int exchan
     }
     HIPCHK(hipStreamSynchronize(h->stream));
     return h->R;
+}
+
+int rfim_set_launch_shape(rfim_t *h, int mode, int nw, int wg) {
+    if (!h) return fail(RFIM_EINVAL, "handle is NULL");
+    if (!rfim_dev::shape_valid(h->L, mode, nw, wg))
+        return fail(RFIM_EINVAL, "launch shape (%d, %d, %d) not valid for L=%d", mode, nw, wg, h->L);
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->mode = mode;
+    h->nw = nw;
+    h->wg = wg;
+    h->nblk = rfim_dev::blocks_per_replica(h->L, mode, nw, wg);
+    return RFIM_OK;
+}
+
+int rfim_get_launch_shape(const rfim_t *h, int *mode, int *nw, int *wg) {
+    if (!h || !mode || !nw || !wg) return fail(RFIM_EINVAL, "NULL argument");
+    *mode = h->mode;
+    *nw = h->nw;
+    *wg = h->wg;
+    return RFIM_OK;
 }
 
 // ---- checkpoint ----------------------------------------------------

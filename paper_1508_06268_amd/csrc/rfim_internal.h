@@ -11,17 +11,19 @@ namespace rfim_dev {
 //   spins  uint8 [R_cap][2][N/2]  colour-split; byte = 1 iff s = +1.
 //          Colour c, sublattice index j holds site 2j or 2j+1 (whichever has
 //          colour c).
-//   fbits  uint8 [2][N/2]         +-1 fields: byte = 1 iff h_i = +1.
+//   fbits  uint8 [2][N/2]         +-1 fields: byte = 4 iff h_i = +1, else 0.
 //   fhf    float [2][N/2]         continuous fields: (float)(h * h_i).
 //   fraw   float [2][N/2]         continuous fields: h_i as given.
-//   thr    uint32 [R_cap][16]     per slot, +-1 fields: threshold by class
-//                                 2k + fb (k = aligned neighbours, fb = field
-//                                 aligned); 0xFFFFFFFF for dE <= 0 classes.
+//   thr    uint32 [R_cap][32]     per slot, +-1 fields: threshold indexed by
+//                                 (up << 2) | (b << 1) | f with up = number of
+//                                 +1 neighbours, b = spin byte, f = field bit;
+//                                 0xFFFFFFFF where dE <= 0 (always accepted).
 //   betaf  float [R_cap]          per slot, continuous fields.
 //   beta   double [R_cap]         per slot (exchange).
 //   t2r, r2t int32 [R_cap]; att, acc uint64 [R_cap]
 //   ctrs   uint64 [2]             global sweep counter t, exchange counter k.
-//   part   double [R_cap][nblk][3] energy partials (B, F, M) per block.
+//   part   double [R_cap][nblk][3] energy partials (B, F, M) per block;
+//                                 nblk = blocks_per_replica(shape).
 //   E      double [R_cap]         energy by replica id after a reduction.
 struct Lattice {
     int L, N, half, R;          // R = replicas currently active
@@ -30,7 +32,7 @@ struct Lattice {
     float Jf;
     double J, h;
     uint32_t key0, key1, rho;
-    uint32_t always_mask;       // bit (2k+fb) set iff that class has dE <= 0
+    uint32_t always_mask;       // bit ((up << 2) | (b << 1) | f) set iff dE <= 0
     uint8_t *spins;
     const uint8_t *fbits;
     const float *fhf, *fraw;
@@ -41,14 +43,33 @@ struct Lattice {
     uint64_t *att, *acc;
     uint64_t *ctrs;
     double *part;
-    int nblk;                   // energy blocks per replica
+    int nblk;                   // energy partials per replica
+    int mode;                   // power-of-two L: 0 streaming, 1 LDS-resident
+    int nw, wg;                 // dwords per thread, threads per workgroup
     double *E;
 };
 
-int energy_blocks_per_replica(int L);
+// Above this many workgroups per replica the streaming sweep does not write
+// energy partials; a separate energy kernel with 64 blocks does.
+constexpr int kMaxFusedBlocks = 1024;
+
+// Launch shapes.  Power-of-two L >= 8: mode 0 (streaming: one chunk of
+// nw dwords per thread, wg in {64, 128, 256}) or mode 1 (LDS-resident,
+// L <= 32: one workgroup of wg threads per replica runs every sweep of an
+// exchange interval).  Other L: generic kernel, shape (0, 0, 0).  Every
+// shape gives bit-identical results.
+bool shape_valid(int L, int mode, int nw, int wg);
+int blocks_per_replica(int L, int mode, int nw, int wg);
 
 hipError_t launch_init(const Lattice &lat, int r0, int r1, hipStream_t s);
-hipError_t launch_sweep(const Lattice &lat, int colour, int toff, hipStream_t s);
+// energy != 0 on a colour-1 launch of a power-of-two lattice also writes
+// the energy partials of the final state (see fused_energy()).
+hipError_t launch_sweep(const Lattice &lat, int colour, int toff, int energy, hipStream_t s);
+// True when the sweep kernel itself writes the energy partials.
+bool fused_energy(const Lattice &lat);
+// mode 1: nsweep whole sweeps of every replica in one launch (energy != 0:
+// also the energy partials of the final state).
+hipError_t launch_resident(const Lattice &lat, int nsweep, int energy, hipStream_t s);
 hipError_t launch_energy(const Lattice &lat, hipStream_t s);
 hipError_t launch_reduce(const Lattice &lat, int64_t *B, double *F, int64_t *M, hipStream_t s);
 hipError_t launch_exchange(const Lattice &lat, int tadv, hipStream_t s);

@@ -28,8 +28,17 @@ __device__ __forceinline__ Words philox10(uint32_t c0, uint32_t c1, uint32_t c2,
     for (int round = 0; round < 10; ++round) {
         const uint64_t a = (uint64_t)0xD2511F53u * c0;
         const uint64_t b = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+        uint32_t n0, n2;
+        if (round < 2) {
+            // the first rounds still hold wave-uniform words: leave them to
+            // the scalar unit
+            n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
+            n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+        } else {
+            // three-input XOR in one VALU instruction (truth table 0x96)
+            n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(b >> 32), c1, k0, 0x96);
+            n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), c3, k1, 0x96);
+        }
         c1 = (uint32_t)b;
         c3 = (uint32_t)a;
         c0 = n0;
@@ -107,10 +116,9 @@ __global__ __launch_bounds__(256) void sweep_generic(Lattice lat, int colour, in
         const uint32_t u = word_at(w, q);
         bool accept;
         if (KIND == 0) {
-            const int k = b ? up : 6 - up;
-            const int fb = b == lat.fbits[(size_t)colour * lat.half + j];
-            const int cls = 2 * k + fb;
-            accept = ((lat.always_mask >> cls) & 1u) || u < lat.thr[slot * 16 + cls];
+            const int f = lat.fbits[(size_t)colour * lat.half + j] >> 2;
+            const int idx = (up << 2) | (b << 1) | f;
+            accept = ((lat.always_mask >> idx) & 1u) || u < lat.thr[slot * 32 + idx];
         } else {
             const float n = (float)(2 * up - 6);
             const float s = b ? 1.0f : -1.0f;
@@ -123,102 +131,343 @@ __global__ __launch_bounds__(256) void sweep_generic(Lattice lat, int colour, in
 }
 
 // ---------------------------------------------------------------------
-// Half-sweep, L = 2^l >= 8.  One thread per four consecutive sublattice
-// sites of one row: the four spin bytes, the six neighbour words and the
-// field bytes are 32-bit loads, and the neighbour counts of the four sites
-// are one packed byte-wise sum (each byte <= 6, so no carries).
+// Half-sweep, L = 2^l >= 8, on one chunk of NW x 4 consecutive sublattice
+// sites of one row (NW Philox blocks): the spin bytes, the six neighbour
+// words and the field bytes are NW-dword loads, and the neighbour counts of
+// four sites are one packed byte-wise sum per dword (each byte <= 6, so no
+// carries).
 //
 // Colour-c site of pair m in row (y, z) sits at x = 2m + p, p = (c+y+z)&1;
 // its x-neighbours of the other colour are pair m and pair m-1+2p of the
-// same row, so the row's other-colour word shifted by one byte (with the
-// byte from the adjacent word, wrapping in the row) supplies the second x
+// same row, so the row's other-colour bytes shifted by one (with one byte
+// from the adjacent dword, wrapping in the row) supply the second x
 // neighbour.
 // ---------------------------------------------------------------------
+template <int NW> struct Vec;
+template <> struct Vec<1> { using T = uint32_t; };
+template <> struct Vec<2> { using T = uint2; };
+template <> struct Vec<4> { using T = uint4; };
+
+template <int NW>
+__device__ __forceinline__ void load_words(const uint8_t *base, uint32_t off, uint32_t (&w)[NW]) {
+    const typename Vec<NW>::T v = *(const typename Vec<NW>::T *)(base + off);
+    if constexpr (NW == 1) {
+        w[0] = v;
+    } else if constexpr (NW == 2) {
+        w[0] = v.x; w[1] = v.y;
+    } else {
+        w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+    }
+}
+
+template <int NW>
+__device__ __forceinline__ void store_words(uint8_t *base, uint32_t off, const uint32_t (&w)[NW]) {
+    typename Vec<NW>::T v;
+    if constexpr (NW == 1) {
+        v = w[0];
+    } else if constexpr (NW == 2) {
+        v.x = w[0]; v.y = w[1];
+    } else {
+        v.x = w[0]; v.y = w[1]; v.z = w[2]; v.w = w[3];
+    }
+    *(typename Vec<NW>::T *)(base + off) = v;
+}
+
+__device__ __forceinline__ int wave_isum(int v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Offsets (in sublattice bytes) of the other-colour words around a chunk.
+struct Chunk {
+    uint32_t p, jxw, jyp, jym, jzp, jzm;
+};
+
+template <int NW>
+__device__ __forceinline__ Chunk chunk_geometry(uint32_t j0, uint32_t colour, uint32_t L, uint32_t l,
+                                                uint32_t half) {
+    Chunk c;
+    const uint32_t hm = (L >> 1) - 1u;          // m bits of j
+    const uint32_t ystep = L >> 1;
+    const uint32_t ymask = (L - 1u) << (l - 1u);
+    const uint32_t zstep = (L * L) >> 1;
+    const uint32_t jmask = half - 1u;
+    const uint32_t m0 = j0 & hm;
+    const uint32_t row = j0 >> (l - 1u);
+    c.p = (colour + row + (row >> l)) & 1u;     // (c + y + z) & 1
+    // the one dword of the adjacent chunk that the x-shift needs
+    c.jxw = (j0 - m0) | ((m0 + (c.p ? 4u * NW : 0u - 4u)) & hm);
+    c.jyp = (j0 & ~ymask) | ((j0 + ystep) & ymask);
+    c.jym = (j0 & ~ymask) | ((j0 - ystep) & ymask);
+    c.jzp = (j0 + zstep) & jmask;
+    c.jzm = (j0 - zstep) & jmask;
+    return c;
+}
+
+// Up-neighbour counts (per byte) of the NW words of a chunk.
+template <int NW>
+__device__ __forceinline__ void neighbour_counts(const uint8_t *oth, uint32_t j0, const Chunk &c,
+                                                 uint32_t (&W)[NW], uint32_t (&U)[NW]) {
+    uint32_t Wyp[NW], Wym[NW], Wzp[NW], Wzm[NW];
+    load_words<NW>(oth, j0, W);
+    const uint32_t Wx = *(const uint32_t *)(oth + c.jxw);
+    load_words<NW>(oth, c.jyp, Wyp);
+    load_words<NW>(oth, c.jym, Wym);
+    load_words<NW>(oth, c.jzp, Wzp);
+    load_words<NW>(oth, c.jzm, Wzm);
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        // p = 1: bytes of pairs m+1..m+4; p = 0: bytes of pairs m-1..m+2
+        const uint32_t nxt = (w + 1 < NW) ? W[w + 1 < NW ? w + 1 : 0] : Wx;
+        const uint32_t prv = (w > 0) ? W[w > 0 ? w - 1 : 0] : Wx;
+        const uint32_t Xs = c.p ? __builtin_amdgcn_alignbyte(nxt, W[w], 1) : __builtin_amdgcn_alignbyte(W[w], prv, 3);
+        U[w] = W[w] + Xs + Wyp[w] + Wym[w] + Wzp[w] + Wzm[w];
+    }
+}
+
+// Metropolis decisions of one Philox block's four sites (+-1 fields): the
+// threshold sits at LDS byte address ((up << 2) | (s << 1) | f) * 4.
+__device__ __forceinline__ uint32_t bimodal_flips(const uint32_t *sthr, uint32_t U, uint32_t Wown,
+                                                  uint32_t F4, const Words &rw, uint32_t always_mask) {
+    const uint32_t A = (U << 4) | (Wown << 3) | F4;
+    const uint8_t *tb = (const uint8_t *)sthr;
+    const uint32_t a0 = A & 0xFFu, a1 = (A >> 8) & 0xFFu, a2 = (A >> 16) & 0xFFu, a3 = A >> 24;
+    const uint32_t th0 = *(const uint32_t *)(tb + a0), th1 = *(const uint32_t *)(tb + a1);
+    const uint32_t th2 = *(const uint32_t *)(tb + a2), th3 = *(const uint32_t *)(tb + a3);
+    uint32_t fl = (rw.w0 < th0 ? 0x1u : 0u) | (rw.w1 < th1 ? 0x100u : 0u) |
+                  (rw.w2 < th2 ? 0x10000u : 0u) | (rw.w3 < th3 ? 0x1000000u : 0u);
+    // A word of 0xFFFFFFFF fails "u < thr" even where dE <= 0, which always
+    // flips: fix those up (about one block in 2^30).
+    const uint32_t umax = max(max(rw.w0, rw.w1), max(rw.w2, rw.w3));
+    if (umax == 0xFFFFFFFFu) {
+        if (rw.w0 == 0xFFFFFFFFu && ((always_mask >> (a0 >> 2)) & 1u)) fl |= 0x1u;
+        if (rw.w1 == 0xFFFFFFFFu && ((always_mask >> (a1 >> 2)) & 1u)) fl |= 0x100u;
+        if (rw.w2 == 0xFFFFFFFFu && ((always_mask >> (a2 >> 2)) & 1u)) fl |= 0x10000u;
+        if (rw.w3 == 0xFFFFFFFFu && ((always_mask >> (a3 >> 2)) & 1u)) fl |= 0x1000000u;
+    }
+    return fl;
+}
+
+// Continuous fields: dE = 2 s (J n + h h_i) and exp(-beta dE) in FP32.
+__device__ __forceinline__ uint32_t continuous_flips(uint32_t U, uint32_t Wown, const float4 hf, float Jf,
+                                                     float beta, const Words &rw) {
+    const float hv[4] = {hf.x, hf.y, hf.z, hf.w};
+    uint32_t fl = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int up = (U >> (8 * q)) & 0xFF;
+        const float n = (float)(2 * up - 6);
+        const float s = ((Wown >> (8 * q)) & 1u) ? 1.0f : -1.0f;
+        const float xloc = Jf * n + hv[q];
+        const float dE = 2.0f * s * xloc;
+        const bool acc = dE <= 0.0f || word_at(rw, q) < cont_threshold(beta, dE);
+        fl |= (acc ? 1u : 0u) << (8 * q);
+    }
+    return fl;
+}
+
+// One chunk's half-sweep update; returns the new own words (and the loaded
+// words the energy pass reuses).
+template <int KIND, int NW>
+__device__ __forceinline__ uint32_t chunk_update(const Lattice &lat, const uint32_t *sthr, uint8_t *own,
+                                                 const uint8_t *oth, const uint8_t *fb_own,
+                                                 const float *hf_own, uint32_t j0, uint32_t g0,
+                                                 uint32_t colour, uint32_t c1, uint32_t r, float beta,
+                                                 uint32_t (&W)[NW], uint32_t (&U)[NW],
+                                                 uint32_t (&Wnew)[NW], uint32_t (&F4)[NW]) {
+    const Chunk c = chunk_geometry<NW>(j0, colour, (uint32_t)lat.L, (uint32_t)lat.log2L, (uint32_t)lat.half);
+    uint32_t Wown[NW];
+    load_words<NW>(own, j0, Wown);
+    neighbour_counts<NW>(oth, j0, c, W, U);
+    if (KIND == 0) load_words<NW>(fb_own, j0, F4);
+    const uint32_t c3 = (kTagSweep << 28) | lat.rho;
+    uint32_t any = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const Words rw = philox10(g0 + (uint32_t)w, c1, r, c3, lat.key0, lat.key1);
+        uint32_t fl;
+        if (KIND == 0) {
+            fl = bimodal_flips(sthr, U[w], Wown[w], F4[w], rw, lat.always_mask);
+        } else {
+            const float4 hf = *(const float4 *)(hf_own + j0 + 4u * w);
+            fl = continuous_flips(U[w], Wown[w], hf, lat.Jf, beta, rw);
+        }
+        any |= fl;
+        Wnew[w] = Wown[w] ^ fl;
+    }
+    return any;
+}
+
+// Energy pieces of a chunk of colour-1 sites and the colour-0 sites of the
+// same pairs, from the final spins: every bond joins a colour-0 and a
+// colour-1 site, so B = sum over colour-1 sites of s_i n_i counts each bond
+// once; F and M take both colours.
+template <int KIND, int NW>
+__device__ __forceinline__ void chunk_energy(const Lattice &lat, const uint32_t (&S1)[NW],
+                                             const uint32_t (&S0)[NW], const uint32_t (&U)[NW],
+                                             const uint32_t (&F1)[NW], const uint8_t *fb0,
+                                             const float *fr1, const float *fr0, uint32_t j0,
+                                             int &ksum, int &upsum, int &eqsum, double &fsum) {
+    uint32_t F0[NW];
+    if (KIND == 0) load_words<NW>(fb0, j0, F0);
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const uint32_t Mb = S1[w] * 0xFFu;                                // 0x00 / 0xFF per byte
+        const uint32_t K = (Mb & U[w]) | (~Mb & (0x06060606u - U[w]));  // aligned neighbours
+        ksum = (int)__builtin_amdgcn_sad_u8(K, 0u, (uint32_t)ksum);
+        upsum = (int)__builtin_amdgcn_sad_u8(S1[w] + S0[w], 0u, (uint32_t)upsum);
+        if (KIND == 0) {
+            const uint32_t e1 = ~(S1[w] ^ (F1[w] >> 2)) & 0x01010101u;
+            const uint32_t e0 = ~(S0[w] ^ (F0[w] >> 2)) & 0x01010101u;
+            eqsum = (int)__builtin_amdgcn_sad_u8(e1 + e0, 0u, (uint32_t)eqsum);
+        } else {
+            const float4 f1 = *(const float4 *)(fr1 + j0 + 4u * w);
+            const float4 f0 = *(const float4 *)(fr0 + j0 + 4u * w);
+            const float a1[4] = {f1.x, f1.y, f1.z, f1.w}, a0[4] = {f0.x, f0.y, f0.z, f0.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                fsum += ((S1[w] >> (8 * q)) & 1u) ? (double)a1[q] : -(double)a1[q];
+                fsum += ((S0[w] >> (8 * q)) & 1u) ? (double)a0[q] : -(double)a0[q];
+            }
+        }
+    }
+}
+
+// Block-wide (B, F, M) partial in a fixed order; thread 0..2 write it.
 template <int KIND>
+__device__ __forceinline__ void block_partial(double *dst, int nsite, int ksum, int upsum, int eqsum,
+                                              double fsum) {
+    __shared__ double red[3][16];
+    const int bpart = 2 * ksum - 6 * nsite;
+    const int mpart = 2 * upsum - 2 * nsite;
+    if (KIND == 0) fsum = (double)(2 * eqsum - 2 * nsite);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int vb = wave_isum(bpart), vm = wave_isum(mpart);
+    const double vf = wave_sum(fsum);
+    if (lane == 0) {
+        red[0][wave] = (double)vb;
+        red[1][wave] = vf;
+        red[2][wave] = (double)vm;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int nw = (int)((blockDim.x + 63) >> 6);
+        double v = red[threadIdx.x][0];
+        for (int q = 1; q < nw; ++q) v += red[threadIdx.x][q];
+        dst[threadIdx.x] = v;
+    }
+}
+
+// Streaming half-sweep: one chunk per thread, all replicas in one launch.
+// ENERGY (colour 1 of the last sweep before an exchange) also writes one
+// energy partial per workgroup.
+template <int KIND, int NW, int ENERGY>
 __global__ __launch_bounds__(256) void sweep_pow2(Lattice lat, int colour, int toff, int wg_per_rep,
                                                    int remap) {
-    __shared__ uint32_t sthr[16];
-    int blk = blockIdx.x;
+    __shared__ uint32_t sthr[32];
+    uint32_t blk = blockIdx.x;
     if (remap) {
         // consecutive block ids go round-robin to the 8 XCDs; give each XCD a
         // contiguous range of tiles so that halo rows stay in its L2
-        const int per = gridDim.x >> 3;
-        blk = (blk & 7) * per + (blk >> 3);
+        const uint32_t per = gridDim.x >> 3;
+        blk = (blk & 7u) * per + (blk >> 3);
     }
-    const int r = blk / wg_per_rep;
-    const int gb = blk - r * wg_per_rep;
+    const uint32_t r = blk / (uint32_t)wg_per_rep;
+    const uint32_t gb = blk - r * (uint32_t)wg_per_rep;
     const int slot = lat.r2t[r];
     if (KIND == 0) {
-        if (threadIdx.x < 16) sthr[threadIdx.x] = lat.thr[slot * 16 + threadIdx.x];
+        if (threadIdx.x < 32) sthr[threadIdx.x] = lat.thr[slot * 32 + threadIdx.x];
         __syncthreads();
     }
-    const int l = lat.log2L;
-    const int L = lat.L;
-    const int g = gb * blockDim.x + threadIdx.x;
-    const int j0 = 4 * g;
-    const int hm = (L >> 1) - 1;                       // m bits
-    const int ystep = L >> 1;
-    const int ymask = (L - 1) << (l - 1);
-    const int zstep = (L * L) >> 1;
-    const int jmask = lat.half - 1;
-    const int m0 = j0 & hm;
-    const int row = j0 >> (l - 1);
-    const int y = row & (L - 1), z = row >> l;
-    const int p = (colour + y + z) & 1;
-    const int jx = (j0 - m0) | ((m0 + (p ? 4 : -4)) & hm);
-    const int jyp = (j0 & ~ymask) | ((j0 + ystep) & ymask);
-    const int jym = (j0 & ~ymask) | ((j0 - ystep) & ymask);
-    const int jzp = (j0 + zstep) & jmask;
-    const int jzm = (j0 - zstep) & jmask;
-
-    uint8_t *own = lat.spins + (size_t)r * lat.N + (size_t)colour * lat.half;
-    const uint8_t *oth = lat.spins + (size_t)r * lat.N + (size_t)(1 - colour) * lat.half;
-    const uint32_t Wown = *(const uint32_t *)(own + j0);
-    const uint32_t W = *(const uint32_t *)(oth + j0);
-    const uint32_t Wx = *(const uint32_t *)(oth + jx);
-    const uint32_t Wyp = *(const uint32_t *)(oth + jyp);
-    const uint32_t Wym = *(const uint32_t *)(oth + jym);
-    const uint32_t Wzp = *(const uint32_t *)(oth + jzp);
-    const uint32_t Wzm = *(const uint32_t *)(oth + jzm);
-    // p = 1: bytes of pairs m0+1..m0+4; p = 0: bytes of pairs m0-1..m0+2
-    const uint32_t Xs = p ? __builtin_amdgcn_alignbyte(Wx, W, 1) : __builtin_amdgcn_alignbyte(W, Wx, 3);
-    const uint32_t U = W + Xs + Wyp + Wym + Wzp + Wzm;  // up-neighbour counts, per byte
-
+    const uint32_t g0 = (gb * blockDim.x + threadIdx.x) * NW;   // first Philox block
+    const uint32_t j0 = 4u * g0;
+    const uint32_t col = (uint32_t)colour;
+    uint8_t *own = lat.spins + (size_t)r * lat.N + (size_t)col * lat.half;
+    const uint8_t *oth = lat.spins + (size_t)r * lat.N + (size_t)(1 - col) * lat.half;
     const uint32_t t = (uint32_t)(lat.ctrs[0] + (uint64_t)toff);
-    const Words w = philox10((uint32_t)g, 2u * t + (uint32_t)colour, (uint32_t)r,
-                             (kTagSweep << 28) | lat.rho, lat.key0, lat.key1);
-    uint32_t flip = 0;
-    if (KIND == 0) {
-        const uint32_t Fw = *(const uint32_t *)(lat.fbits + (size_t)colour * lat.half + j0);
-        const uint32_t Mb = Wown * 0xFFu;                      // 0x00 / 0xFF per byte
-        const uint32_t K = (Mb & U) | (~Mb & (0x06060606u - U)); // aligned neighbours
-        const uint32_t FB = ~(Wown ^ Fw) & 0x01010101u;         // field aligned
-        const uint32_t CLS = (K << 1) | FB;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint32_t cls = (CLS >> (8 * q)) & 0xFFu;
-            const uint32_t u = word_at(w, q);
-            uint32_t acc = u < sthr[cls] ? 1u : 0u;
-            if (u == 0xFFFFFFFFu) acc = (lat.always_mask >> cls) & 1u;
-            flip |= acc << (8 * q);
-        }
-    } else {
-        const float4 hf = *(const float4 *)(lat.fhf + (size_t)colour * lat.half + j0);
-        const float beta = lat.betaf[slot];
-        const float hv[4] = {hf.x, hf.y, hf.z, hf.w};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int up = (U >> (8 * q)) & 0xFF;
-            const float n = (float)(2 * up - 6);
-            const float s = ((Wown >> (8 * q)) & 1u) ? 1.0f : -1.0f;
-            const float xloc = lat.Jf * n + hv[q];
-            const float dE = 2.0f * s * xloc;
-            const uint32_t u = word_at(w, q);
-            const bool acc = dE <= 0.0f || u < cont_threshold(beta, dE);
-            flip |= (acc ? 1u : 0u) << (8 * q);
+    const float beta = KIND == 1 ? lat.betaf[slot] : 0.0f;
+    uint32_t W[NW], U[NW], Wnew[NW], F4[NW];
+    const uint32_t any = chunk_update<KIND, NW>(
+        lat, sthr, own, oth, KIND == 0 ? lat.fbits + (size_t)col * lat.half : nullptr,
+        KIND == 1 ? lat.fhf + (size_t)col * lat.half : nullptr, j0, g0, col, 2u * t + col, r, beta, W, U,
+        Wnew, F4);
+    if (any) store_words<NW>(own, j0, Wnew);
+    if (ENERGY) {
+        int ksum = 0, upsum = 0, eqsum = 0;
+        double fsum = 0.0;
+        chunk_energy<KIND, NW>(lat, Wnew, W, U, F4, KIND == 0 ? lat.fbits : nullptr,
+                               KIND == 1 ? lat.fraw + lat.half : nullptr, KIND == 1 ? lat.fraw : nullptr,
+                               j0, ksum, upsum, eqsum, fsum);
+        block_partial<KIND>(lat.part + ((size_t)r * lat.nblk + gb) * 3, 4 * NW, ksum, upsum, eqsum, fsum);
+    }
+}
+
+// Resident sweeps (L = 2^l <= 32): one workgroup holds one replica's spins
+// in LDS and runs `nsweep` whole sweeps (colour 0 then colour 1, a barrier
+// between half-sweeps), then, if asked, the energy partial of the final
+// state, and writes the spins back.  Fields stay in global memory (shared
+// by every replica, so they live in L2).
+template <int KIND, int NW>
+__global__ __launch_bounds__(1024) void sweep_resident(Lattice lat, int nsweep, int energy) {
+    extern __shared__ uint4 lds_raw[];
+    __shared__ uint32_t sthr[32];
+    uint8_t *sp = (uint8_t *)lds_raw;                  // [2][half]
+    const uint32_t r = blockIdx.x;
+    const uint32_t N = (uint32_t)lat.N, half = (uint32_t)lat.half;
+    const int slot = lat.r2t[r];
+    const uint4 *src = (const uint4 *)(lat.spins + (size_t)r * N);
+    for (uint32_t q = threadIdx.x; q < N / 16u; q += blockDim.x) lds_raw[q] = src[q];
+    if (KIND == 0 && threadIdx.x < 32) sthr[threadIdx.x] = lat.thr[slot * 32 + threadIdx.x];
+    const float beta = KIND == 1 ? lat.betaf[slot] : 0.0f;
+    const uint32_t t0 = (uint32_t)lat.ctrs[0];
+    const uint32_t nchunk = half / (4u * NW);
+    __syncthreads();
+    for (int sw = 0; sw < nsweep; ++sw) {
+        for (uint32_t col = 0; col < 2; ++col) {
+            uint8_t *own = sp + col * half;
+            const uint8_t *oth = sp + (1u - col) * half;
+            const uint32_t c1 = 2u * (t0 + (uint32_t)sw) + col;
+            for (uint32_t ch = threadIdx.x; ch < nchunk; ch += blockDim.x) {
+                const uint32_t g0 = ch * NW, j0 = 4u * g0;
+                uint32_t W[NW], U[NW], Wnew[NW], F4[NW];
+                const uint32_t any = chunk_update<KIND, NW>(
+                    lat, sthr, own, oth, KIND == 0 ? lat.fbits + (size_t)col * half : nullptr,
+                    KIND == 1 ? lat.fhf + (size_t)col * half : nullptr, j0, g0, col, c1, r, beta, W, U,
+                    Wnew, F4);
+                if (any) store_words<NW>(own, j0, Wnew);
+            }
+            __syncthreads();
         }
     }
-    if (flip) *(uint32_t *)(own + j0) = Wown ^ flip;
+    if (energy) {
+        int ksum = 0, upsum = 0, eqsum = 0;
+        double fsum = 0.0;
+        const uint8_t *s1 = sp + half, *s0 = sp;
+        for (uint32_t ch = threadIdx.x; ch < nchunk; ch += blockDim.x) {
+            const uint32_t j0 = 4u * NW * ch;
+            const Chunk c = chunk_geometry<NW>(j0, 1u, (uint32_t)lat.L, (uint32_t)lat.log2L, half);
+            uint32_t S1[NW], W[NW], U[NW], F1[NW];
+            load_words<NW>(s1, j0, S1);
+            neighbour_counts<NW>(s0, j0, c, W, U);
+            if (KIND == 0) load_words<NW>(lat.fbits + half, j0, F1);
+            chunk_energy<KIND, NW>(lat, S1, W, U, F1, KIND == 0 ? lat.fbits : nullptr,
+                                   KIND == 1 ? lat.fraw + half : nullptr, KIND == 1 ? lat.fraw : nullptr,
+                                   j0, ksum, upsum, eqsum, fsum);
+        }
+        // every thread covered 4*NW sites per chunk it took; nsite per thread
+        // differs, so fold the affine offsets into the total instead
+        const int nch = (int)((nchunk > threadIdx.x) ? (nchunk - 1 - threadIdx.x) / blockDim.x + 1 : 0);
+        block_partial<KIND>(lat.part + (size_t)r * lat.nblk * 3, 4 * NW * nch, ksum, upsum, eqsum, fsum);
+    }
+    uint4 *dst = (uint4 *)(lat.spins + (size_t)r * N);
+    for (uint32_t q = threadIdx.x; q < N / 16u; q += blockDim.x) dst[q] = lds_raw[q];
 }
 
 // ---------------------------------------------------------------------
@@ -226,12 +475,6 @@ __global__ __launch_bounds__(256) void sweep_pow2(Lattice lat, int colour, int t
 // site, so B = sum over colour-1 sites of s_i n_i counts each bond once;
 // F and M run over both colours.  Grid (nblk, R); fixed reduction order.
 // ---------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
 __global__ __launch_bounds__(256) void energy_kernel(Lattice lat) {
     const int G = lat.half >> 2;
     const int r = blockIdx.y;
@@ -257,7 +500,7 @@ __global__ __launch_bounds__(256) void energy_kernel(Lattice lat) {
             bsum += sp1 * (2 * up - 6);
             msum += sp1 + sp0;
             if (lat.kind == 0) {
-                const int f1 = 2 * lat.fbits[lat.half + j] - 1, f0 = 2 * lat.fbits[j] - 1;
+                const int f1 = (lat.fbits[lat.half + j] >> 1) - 1, f0 = (lat.fbits[j] >> 1) - 1;
                 fsum += (double)(f1 * sp1 + f0 * sp0);
             } else {
                 fsum += (double)lat.fraw[lat.half + j] * (double)sp1;
@@ -281,33 +524,32 @@ __global__ __launch_bounds__(256) void energy_kernel(Lattice lat) {
     }
 }
 
-__device__ __forceinline__ void replica_totals(const Lattice &lat, int r, double &B, double &F,
-                                               double &M) {
-    const double *pp = lat.part + (size_t)r * lat.nblk * 3;
-    B = 0.0;
-    F = 0.0;
-    M = 0.0;
-    for (int b = 0; b < lat.nblk; ++b) {
-        B += pp[3 * b + 0];
-        F += pp[3 * b + 1];
-        M += pp[3 * b + 2];
-    }
-}
-
 __device__ __forceinline__ double energy_of(const Lattice &lat, double B, double F) {
     return -(lat.J * B) - (lat.h * F);
 }
 
-// Totals per replica id; optional outputs for the observables calls.
+// Totals per replica id; optional outputs for the observables calls.  Same
+// summation order as the exchange kernel.
 __global__ __launch_bounds__(256) void reduce_kernel(Lattice lat, int64_t *Bout, double *Fout,
                                                      int64_t *Mout) {
-    for (int r = threadIdx.x; r < lat.R; r += 256) {
-        double B, F, M;
-        replica_totals(lat, r, B, F, M);
-        lat.E[r] = energy_of(lat, B, F);
-        if (Bout) Bout[r] = (int64_t)B;
-        if (Fout) Fout[r] = F;
-        if (Mout) Mout[r] = (int64_t)M;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int r = wave; r < lat.R; r += 4) {
+        const double *pp = lat.part + (size_t)r * lat.nblk * 3;
+        double B = 0.0, F = 0.0, M = 0.0;
+        for (int b = lane; b < lat.nblk; b += 64) {
+            B += pp[3 * b + 0];
+            F += pp[3 * b + 1];
+            M += pp[3 * b + 2];
+        }
+        B = wave_sum(B);
+        F = wave_sum(F);
+        M = wave_sum(M);
+        if (lane == 0) {
+            lat.E[r] = energy_of(lat, B, F);
+            if (Bout) Bout[r] = (int64_t)B;
+            if (Fout) Fout[r] = F;
+            if (Mout) Mout[r] = (int64_t)M;
+        }
     }
 }
 
@@ -316,10 +558,19 @@ __global__ __launch_bounds__(256) void reduce_kernel(Lattice lat, int64_t *Bout,
 // move through t2r / r2t (Sec. 3.3).  One workgroup.
 // ---------------------------------------------------------------------
 __global__ __launch_bounds__(256) void exchange_kernel(Lattice lat, int tadv) {
-    for (int r = threadIdx.x; r < lat.R; r += 256) {
-        double B, F, M;
-        replica_totals(lat, r, B, F, M);
-        lat.E[r] = energy_of(lat, B, F);
+    // energies: one wave per replica, lanes stride the partials in a fixed
+    // order, then a fixed butterfly
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int r = wave; r < lat.R; r += 4) {
+        const double *pp = lat.part + (size_t)r * lat.nblk * 3;
+        double B = 0.0, F = 0.0;
+        for (int b = lane; b < lat.nblk; b += 64) {
+            B += pp[3 * b + 0];
+            F += pp[3 * b + 1];
+        }
+        B = wave_sum(B);
+        F = wave_sum(F);
+        if (lane == 0) lat.E[r] = energy_of(lat, B, F);
     }
     const uint64_t k = lat.ctrs[1];
     __syncthreads();
@@ -351,11 +602,43 @@ __global__ void advance_kernel(uint64_t *ctrs, int tadv) {
 
 }  // namespace
 
-int energy_blocks_per_replica(int L) {
-    const long long G = (long long)L * L * L / 8;
-    long long nb = (G + 255) / 256;
-    if (nb > 64) nb = 64;
-    return (int)(nb < 1 ? 1 : nb);
+bool shape_valid(int L, int mode, int nw, int wg) {
+    const bool pow2 = L >= 8 && (L & (L - 1)) == 0;
+    if (!pow2) return mode == 0 && nw == 0 && wg == 0;      // generic kernel, fixed shape
+    if (nw != 1 && nw != 2 && nw != 4) return false;
+    if (4 * nw > L / 2) return false;                        // a chunk lies inside one row
+    const long long chunks = (long long)L * L * L / 8 / nw;  // per colour and replica
+    if (mode == 0) {
+        if (wg != 64 && wg != 128 && wg != 256) return false;
+        return chunks % wg == 0 || chunks < wg;
+    }
+    if (mode == 1) {
+        if (L > 32) return false;                            // one replica must fit in LDS
+        return wg == 64 || wg == 128 || wg == 256 || wg == 512 || wg == 1024;
+    }
+    return false;
+}
+
+int blocks_per_replica(int L, int mode, int nw, int wg) {
+    const bool pow2 = L >= 8 && (L & (L - 1)) == 0;
+    if (!pow2) {
+        const long long G = (long long)L * L * L / 8;
+        long long nb = (G + 255) / 256;
+        if (nb > 64) nb = 64;
+        return (int)(nb < 1 ? 1 : nb);
+    }
+    if (mode == 1) return 1;
+    const long long chunks = (long long)L * L * L / 8 / nw;
+    if (chunks < wg) return 1;
+    const long long nb = chunks / wg;
+    return nb > kMaxFusedBlocks ? 64 : (int)nb;
+}
+
+bool fused_energy(const Lattice &lat) {
+    if (lat.log2L < 3) return false;
+    if (lat.mode == 1) return true;
+    const long long chunks = (long long)lat.N / 8 / lat.nw;
+    return chunks <= (long long)lat.wg * kMaxFusedBlocks;
 }
 
 hipError_t launch_init(const Lattice &lat, int r0, int r1, hipStream_t s) {
@@ -366,19 +649,43 @@ hipError_t launch_init(const Lattice &lat, int r0, int r1, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(const Lattice &lat, int colour, int toff, hipStream_t s) {
+template <int KIND, int ENERGY>
+static void launch_pow2(const Lattice &lat, int colour, int toff, hipStream_t s) {
+    const long long chunks = (long long)lat.N / 8 / lat.nw;
+    const int wg = chunks < lat.wg ? (int)chunks : lat.wg;
+    const int wpr = (int)(chunks / wg);
+    const int nb = wpr * lat.R;
+    const int remap = (nb % 8 == 0) ? 1 : 0;
+    if (lat.nw == 4)
+        hipLaunchKernelGGL((sweep_pow2<KIND, 4, ENERGY>), dim3(nb), dim3(wg), 0, s, lat, colour, toff, wpr, remap);
+    else if (lat.nw == 2)
+        hipLaunchKernelGGL((sweep_pow2<KIND, 2, ENERGY>), dim3(nb), dim3(wg), 0, s, lat, colour, toff, wpr, remap);
+    else
+        hipLaunchKernelGGL((sweep_pow2<KIND, 1, ENERGY>), dim3(nb), dim3(wg), 0, s, lat, colour, toff, wpr, remap);
+}
+
+template <int KIND>
+static void launch_res(const Lattice &lat, int nsweep, int energy, hipStream_t s) {
+    const size_t lds = (size_t)lat.N;
+    if (lat.nw == 4)
+        hipLaunchKernelGGL((sweep_resident<KIND, 4>), dim3(lat.R), dim3(lat.wg), lds, s, lat, nsweep, energy);
+    else if (lat.nw == 2)
+        hipLaunchKernelGGL((sweep_resident<KIND, 2>), dim3(lat.R), dim3(lat.wg), lds, s, lat, nsweep, energy);
+    else
+        hipLaunchKernelGGL((sweep_resident<KIND, 1>), dim3(lat.R), dim3(lat.wg), lds, s, lat, nsweep, energy);
+}
+
+hipError_t launch_sweep(const Lattice &lat, int colour, int toff, int energy, hipStream_t s) {
     const int G = lat.half >> 2;
     if (lat.log2L >= 3) {
-        const int wg = G < 256 ? G : 256;
-        const int wg_per_rep = G / wg;
-        const int nb = wg_per_rep * lat.R;
-        const int remap = (nb % 8 == 0) ? 1 : 0;
-        if (lat.kind == 0)
-            hipLaunchKernelGGL(sweep_pow2<0>, dim3(nb), dim3(wg), 0, s, lat, colour, toff, wg_per_rep,
-                               remap);
-        else
-            hipLaunchKernelGGL(sweep_pow2<1>, dim3(nb), dim3(wg), 0, s, lat, colour, toff, wg_per_rep,
-                               remap);
+        const bool e = energy && colour == 1 && fused_energy(lat);
+        if (lat.kind == 0) {
+            if (e) launch_pow2<0, 1>(lat, colour, toff, s);
+            else launch_pow2<0, 0>(lat, colour, toff, s);
+        } else {
+            if (e) launch_pow2<1, 1>(lat, colour, toff, s);
+            else launch_pow2<1, 0>(lat, colour, toff, s);
+        }
     } else {
         dim3 grid((G + 255) / 256, lat.R);
         if (lat.kind == 0)
@@ -386,6 +693,12 @@ hipError_t launch_sweep(const Lattice &lat, int colour, int toff, hipStream_t s)
         else
             hipLaunchKernelGGL(sweep_generic<1>, grid, dim3(256), 0, s, lat, colour, toff);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_resident(const Lattice &lat, int nsweep, int energy, hipStream_t s) {
+    if (lat.kind == 0) launch_res<0>(lat, nsweep, energy, s);
+    else launch_res<1>(lat, nsweep, energy, s);
     return hipGetLastError();
 }
 

@@ -27,6 +27,7 @@ EXPORTS = [
     "rfim_magnetizations", "rfim_components", "rfim_get_spins", "rfim_set_spins",
     "rfim_get_perm", "rfim_set_perm", "rfim_get_counters", "rfim_set_counters",
     "rfim_exchange_stats", "rfim_reset_exchange_stats", "rfim_save", "rfim_load",
+    "rfim_set_launch_shape", "rfim_get_launch_shape",
 ]
 
 
@@ -85,6 +86,8 @@ def load_library(path: str = LIB_PATH):
         "rfim_reset_exchange_stats": (i32, [vp]),
         "rfim_save": (i32, [vp, vp, C.POINTER(sz)]),
         "rfim_load": (vp, [vp, sz, vp]),
+        "rfim_set_launch_shape": (i32, [vp, i32, i32, i32]),
+        "rfim_get_launch_shape": (i32, [vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -272,6 +275,14 @@ class Rfim:
                     R_cap):
         return rfim_adapt_temps(self._h, trials, sweeps_per_trial, every, rate_threshold,
                                 max_insert_per_trial, R_cap)
+
+    def launch_shape(self):
+        m, nw, wg = C.c_int(), C.c_int(), C.c_int()
+        _check(load_library().rfim_get_launch_shape(self._h, C.byref(m), C.byref(nw), C.byref(wg)))
+        return m.value, nw.value, wg.value
+
+    def set_launch_shape(self, mode, nw, wg):
+        _check(load_library().rfim_set_launch_shape(self._h, int(mode), int(nw), int(wg)))
 
     def save(self) -> bytes:
         n = C.c_size_t(0)

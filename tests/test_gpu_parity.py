@@ -110,3 +110,61 @@ def test_repeat_runs_identical(rfim_mod):
     assert np.array_equal(runs[0][0], runs[1][0])
     assert np.array_equal(runs[0][1], runs[1][1])
     assert np.array_equal(runs[0][2], runs[1][2])
+
+
+SHAPES = {
+    8: [(0, 1, 64), (1, 1, 64), (1, 1, 256), (0, 1, 256)],
+    16: [(0, 1, 256), (0, 2, 128), (1, 2, 256), (1, 1, 1024), (1, 2, 64)],
+    32: [(0, 4, 256), (0, 1, 64), (0, 2, 128), (1, 4, 1024), (1, 2, 512), (1, 1, 256)],
+    64: [(0, 4, 256), (0, 2, 128), (0, 1, 64), (0, 4, 64)],
+}
+
+
+@pytest.mark.parametrize("L", sorted(SHAPES))
+def test_every_launch_shape_matches_oracle(rfim_mod, oracle_mod, L):
+    """Streaming and LDS-resident kernels, every dwords-per-thread and
+    workgroup size: the same chain, bit for bit (+-1 fields)."""
+    R = 4 if L == 64 else 6
+    f = W.bimodal_fields(L, [16, L])
+    T = W.linear_temps(R, 1.0, 5.0)
+    o = oracle_mod.Oracle(L, R, 1.0, 1.5, f, T, seed=21)
+    o.sweep(25, 10)
+    for shape in SHAPES[L]:
+        g = rfim_mod.Rfim(L, R, 1.0, 1.5, f, T, seed=21)
+        g.set_launch_shape(*shape)
+        assert g.launch_shape() == shape
+        g.sweep(25, 10)
+        assert_same_state(g, o, "L=%d shape %s" % (L, shape))
+        g.close()
+
+
+@pytest.mark.parametrize("L", [16, 32])
+def test_launch_shapes_agree_continuous(rfim_mod, L):
+    R = 5
+    f = W.gaussian_fields(L, [17, L])
+    T = W.geometric_temps(R, 1.0, 6.0)
+    ref = None
+    for shape in SHAPES[L]:
+        g = rfim_mod.Rfim(L, R, 1.0, 2.0, f, T, seed=4)
+        g.set_launch_shape(*shape)
+        g.sweep(30, 10)
+        state = (g.spins(), g.perm(), g.energies())
+        g.close()
+        if ref is None:
+            ref = state
+            continue
+        assert np.array_equal(ref[0], state[0]), shape
+        assert np.array_equal(ref[1], state[1]), shape
+        # FP64 sums of per-workgroup partials: same values up to rounding order
+        assert np.allclose(ref[2], state[2], rtol=1e-13, atol=1e-9), shape
+
+
+def test_invalid_launch_shape_rejected(rfim_mod):
+    f = W.bimodal_fields(16, [0, 0])
+    g = rfim_mod.Rfim(16, 2, 1.0, 1.0, f, [1.0, 2.0])
+    for bad in [(1, 4, 64), (0, 3, 64), (0, 1, 512), (2, 1, 64)]:
+        with pytest.raises(rfim_mod.RfimError):
+            g.set_launch_shape(*bad)
+    g64 = rfim_mod.Rfim(64, 1, 1.0, 1.0, W.bimodal_fields(64, [0, 0]), [1.0])
+    with pytest.raises(rfim_mod.RfimError):
+        g64.set_launch_shape(1, 4, 1024)       # a 64^3 replica does not fit in LDS
