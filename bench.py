@@ -36,6 +36,17 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_pow2_l64_r192_traffic.txt")
 # spins: read the site (1), read the other colour once (1), read the field
 # (1 for +-1 fields, 4 for FP32 fields), write the site (1).
 BYTES_PER_ATTEMPT = {0: 4.0, 1: 7.0}
+# The half-sweep is bound by the vector ALU (Philox4x32-10), so its roofline
+# is the VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12
+# full-rate 32-bit lane-op slots per second.  Algorithmic slots per attempt
+# (+-1 fields), with the cheapest gfx950 instruction for each required step:
+#   Philox block (4 attempts): 20 products 32x32->64 at 2 slots + 20 XOR3
+#     at 1 slot = 60 slots;
+#   Metropolis on four packed sites: neighbour counts 3, threshold index 2,
+#     per-site byte extract 4, compare 4, flip assembly 4, new word 1 = 18.
+#   (60 + 18) / 4 = 19.5 slots per attempt.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+VALU_SLOTS_PER_ATTEMPT = 19.5
 
 
 def log(msg):
@@ -90,6 +101,28 @@ def cpu_baseline(w, sweeps=20):
                       % (w.L, w.R, sweeps, w.every, att, dt)}
 
 
+def kernel_only(torch, P, W, sweeps):
+    """Only the dominant kernel at the production shape (L=64, R=192, +-1
+    fields): `sweeps` sweeps without exchange, for counter collection."""
+    w = W.adaptive_l64()
+    stream = torch.cuda.Stream()
+    h = P.Rfim(w.L, w.R_cap, w.J, w.h, w.fields, W.linear_temps(w.R_cap, 1.0, 6.0), seed=w.seed,
+               stream=stream)
+    h.sweep(sweeps, 0)
+    h.synchronize()
+    log("kernel mode: %d half-sweep launches at L=%d R=%d" % (2 * sweeps, w.L, w.R_cap))
+
+
+def copy_only(torch, nbytes, reps=5):
+    """A plain device-to-device copy of known size (counter calibration)."""
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("copy mode: %d copies of %d bytes (read %d, write %d per copy)" % (reps, nbytes, nbytes, nbytes))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +131,10 @@ def main():
     ap.add_argument("--workload", default="adaptive_l64", choices=["adaptive_l64"])
     ap.add_argument("--production-sweeps", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="bench", choices=["bench", "kernel", "copy"],
+                    help="kernel: only the dominant kernel (for counters); copy: a plain copy "
+                         "of --copy-bytes (counter calibration)")
+    ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs a realization on a single MI355X "
@@ -110,6 +147,12 @@ def main():
     from paper_1508_06268_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.mode == "kernel":
+        kernel_only(torch, P, W, 20)
+        return
+    if args.mode == "copy":
+        copy_only(torch, args.copy_bytes)
+        return
     w = W.adaptive_l64(sweeps=args.production_sweeps)
     stream = torch.cuda.Stream()
     log("creating %d handles: L=%d R=%d R_cap=%d" % (args.warmup + args.steps, w.L, w.R, w.R_cap))
@@ -160,14 +203,21 @@ def main():
     kind = h.field_kind
     attempts_per_launch = R_final * w.L ** 3 // 2
     bytes_per_launch = BYTES_PER_ATTEMPT[kind] * attempts_per_launch
-    achieved = bytes_per_launch / (launch_us * 1e-6) / 1e9
+    hbm_gbs = bytes_per_launch / (launch_us * 1e-6) / 1e9
+    alu_tops = VALU_SLOTS_PER_ATTEMPT * attempts_per_launch / (launch_us * 1e-6) / 1e12
     traffic = measured_traffic(bytes_per_launch)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "sweep_pow2<bimodal>", "launch_us": round(launch_us, 3),
-                "bytes_per_launch": bytes_per_launch, "attempts_per_ns_kernel":
-                    round(attempts_per_launch / (launch_us * 1e3), 1)}
-    log("roofline: %.2f us per half-sweep launch, %.0f GB/s algorithmic" % (launch_us, achieved))
+    roofline = {"bound": "alu", "achieved": round(alu_tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
+                "unit": "TOP/s", "frac": round(alu_tops / VALU_PEAK_TOPS, 4), "traffic": traffic,
+                "kernel": "sweep_pow2<bimodal, 4 dwords/thread>", "launch_us": round(launch_us, 3),
+                "attempts_per_launch": attempts_per_launch,
+                "ops_per_attempt": VALU_SLOTS_PER_ATTEMPT,
+                "attempts_per_ns_kernel": round(attempts_per_launch / (launch_us * 1e3), 1),
+                "hbm": {"achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
+                        "bytes_per_launch": bytes_per_launch, "bytes_per_attempt": BYTES_PER_ATTEMPT[kind]}}
+    log("roofline: %.2f us per half-sweep launch, %.0f GB/s algorithmic (%.1f%% of HBM), "
+        "%.1f TOP/s VALU (%.1f%%)" % (launch_us, hbm_gbs, 100 * hbm_gbs / HBM_PEAK_GBS, alu_tops,
+                                       100 * alu_tops / VALU_PEAK_TOPS))
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -528,28 +528,31 @@ __device__ __forceinline__ double energy_of(const Lattice &lat, double B, double
     return -(lat.J * B) - (lat.h * F);
 }
 
-// Totals per replica id; optional outputs for the observables calls.  Same
-// summation order as the exchange kernel.
+// Partials of replica r summed in block order (one lane per replica; the
+// same order everywhere, so FP64 totals are reproducible).
+__device__ __forceinline__ void replica_totals(const Lattice &lat, int r, double &B, double &F, double &M) {
+    const double *pp = lat.part + (size_t)r * lat.nblk * 3;
+    B = 0.0;
+    F = 0.0;
+    M = 0.0;
+#pragma unroll 8
+    for (int b = 0; b < lat.nblk; ++b) {
+        B += pp[3 * b + 0];
+        F += pp[3 * b + 1];
+        M += pp[3 * b + 2];
+    }
+}
+
+// Totals per replica id; optional outputs for the observables calls.
 __global__ __launch_bounds__(256) void reduce_kernel(Lattice lat, int64_t *Bout, double *Fout,
                                                      int64_t *Mout) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int r = wave; r < lat.R; r += 4) {
-        const double *pp = lat.part + (size_t)r * lat.nblk * 3;
-        double B = 0.0, F = 0.0, M = 0.0;
-        for (int b = lane; b < lat.nblk; b += 64) {
-            B += pp[3 * b + 0];
-            F += pp[3 * b + 1];
-            M += pp[3 * b + 2];
-        }
-        B = wave_sum(B);
-        F = wave_sum(F);
-        M = wave_sum(M);
-        if (lane == 0) {
-            lat.E[r] = energy_of(lat, B, F);
-            if (Bout) Bout[r] = (int64_t)B;
-            if (Fout) Fout[r] = F;
-            if (Mout) Mout[r] = (int64_t)M;
-        }
+    for (int r = threadIdx.x; r < lat.R; r += 256) {
+        double B, F, M;
+        replica_totals(lat, r, B, F, M);
+        lat.E[r] = energy_of(lat, B, F);
+        if (Bout) Bout[r] = (int64_t)B;
+        if (Fout) Fout[r] = F;
+        if (Mout) Mout[r] = (int64_t)M;
     }
 }
 
@@ -558,19 +561,10 @@ __global__ __launch_bounds__(256) void reduce_kernel(Lattice lat, int64_t *Bout,
 // move through t2r / r2t (Sec. 3.3).  One workgroup.
 // ---------------------------------------------------------------------
 __global__ __launch_bounds__(256) void exchange_kernel(Lattice lat, int tadv) {
-    // energies: one wave per replica, lanes stride the partials in a fixed
-    // order, then a fixed butterfly
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int r = wave; r < lat.R; r += 4) {
-        const double *pp = lat.part + (size_t)r * lat.nblk * 3;
-        double B = 0.0, F = 0.0;
-        for (int b = lane; b < lat.nblk; b += 64) {
-            B += pp[3 * b + 0];
-            F += pp[3 * b + 1];
-        }
-        B = wave_sum(B);
-        F = wave_sum(F);
-        if (lane == 0) lat.E[r] = energy_of(lat, B, F);
+    for (int r = threadIdx.x; r < lat.R; r += 256) {
+        double B, F, M;
+        replica_totals(lat, r, B, F, M);
+        lat.E[r] = energy_of(lat, B, F);
     }
     const uint64_t k = lat.ctrs[1];
     __syncthreads();
