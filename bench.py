@@ -123,6 +123,56 @@ def copy_only(torch, nbytes, reps=5):
     log("copy mode: %d copies of %d bytes (read %d, write %d per copy)" % (reps, nbytes, nbytes, nbytes))
 
 
+def batched_leg(torch, P, W, n=256, sweeps=5000, every=10):
+    """Many realizations of uneven L and R in one batch (one launch per
+    class and half-sweep or interval, graph-replayed intervals, autotuned
+    shapes) against the same realizations run one at a time through
+    rfim_create/rfim_sweep on the same GPU.  Handles and batch are created
+    before the timed regions; each timed region ends when every result
+    (energies by slot) is back on the host."""
+    from paper_1508_06268_amd import autotune
+
+    specs = W.batched_mix(n, sweeps)
+    attempts = sum(w.R * w.L ** 3 for w in specs) * sweeps
+    log("batched: %d realizations, %.2e attempts; tuning shapes" % (n, attempts))
+    shapes = autotune.tune(specs, every=every, log=None)
+    stream = torch.cuda.Stream()
+    b = P.Batch(specs, stream=stream)
+    autotune.apply(b, shapes)
+    b.sweep(every, every)                  # graph capture outside the timed region
+    b.synchronize()
+    t0 = time.perf_counter()
+    b.sweep(sweeps - every, every)
+    b.synchronize()
+    E = [b.item(q).energies() for q in range(n)]
+    t_batch = time.perf_counter() - t0
+    att_batch = sum(w.R * w.L ** 3 for w in specs) * (sweeps - every)
+    b.close()
+    log("batched: %.3f s -> %.1f realizations/s" % (t_batch, n / t_batch))
+    singles = [P.Rfim(w.L, w.R, w.J, w.h, w.fields, w.temps, seed=w.seed, realization=w.realization,
+                      stream=stream) for w in specs]
+    for h in singles:
+        h.sweep(every, every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for h in singles:
+        h.sweep(sweeps - every, every)
+        h.energies()
+    t_single = time.perf_counter() - t0
+    for h in singles:
+        h.close()
+    log("one at a time: %.3f s -> %.1f realizations/s" % (t_single, n / t_single))
+    assert len(E) == n
+    return {"workload": "batched_mix", "realizations": n, "sweeps": sweeps - every,
+            "exchange_every": every, "L": [8, 16, 32], "R": [16, 32, 64],
+            "batched_realizations_per_s": round(n / t_batch, 2),
+            "batched_attempts_per_ns": round(att_batch / t_batch / 1e9, 1),
+            "single_loop_realizations_per_s": round(n / t_single, 2),
+            "speedup_vs_single_loop": round(t_single / t_batch, 2),
+            "shapes": {"L%d_%s" % (L, "pm1" if k == 0 else "gauss"): list(s)
+                       for (L, k), s in sorted(shapes.items())}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +185,7 @@ def main():
                     help="kernel: only the dominant kernel (for counters); copy: a plain copy "
                          "of --copy-bytes (counter calibration)")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-realizations leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs a realization on a single MI355X "
@@ -219,6 +270,10 @@ def main():
         "%.1f TOP/s VALU (%.1f%%)" % (launch_us, hbm_gbs, 100 * hbm_gbs / HBM_PEAK_GBS, alu_tops,
                                        100 * alu_tops / VALU_PEAK_TOPS))
 
+    for hh in handles:
+        hh.close()
+    batched = None if args.no_batched else batched_leg(torch, P, W)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a bounded sample")
@@ -237,6 +292,7 @@ def main():
                    "attempts_per_step": attempts // args.steps},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
 

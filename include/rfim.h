@@ -178,6 +178,39 @@ int rfim_get_launch_shape(const rfim_t *h, int *mode, int *nw, int *wg);
 int rfim_save(rfim_t *h, void *buf, size_t *len);
 rfim_t *rfim_load(const void *buf, size_t len, void *hip_stream);
 
+/* ---- batches: many independent realizations per launch ------------- */
+
+/*
+ * A batch advances n independent realizations together (realization-level
+ * parallelism, the natural choice the paper sets aside for single large
+ * lattices in Sec. 8).  Every item must have L a power of two >= 8; items
+ * may differ in L, R, J, h, field kind, seed and realization id.  Items that
+ * share (L, field kind) form a class whose sweeps run in one launch (one per
+ * half-sweep when streaming, one per exchange interval when LDS-resident);
+ * one launch runs the exchange steps of all items; a full exchange interval
+ * is captured once as a HIP graph and replayed.  Each item's chain is
+ * bit-identical to the same realization run alone with rfim_create_ex.
+ *   items      host [n] parameter blocks (copied); n in [1, 65536].
+ *   hip_stream caller's hipStream_t or NULL (the batch creates its own).
+ * Returns NULL on failure.
+ */
+typedef struct rfim_batch rfim_batch_t;
+rfim_batch_t *rfim_batch_create(int n, const rfim_params_t *items, void *hip_stream);
+void rfim_batch_destroy(rfim_batch_t *b);
+int rfim_batch_size(const rfim_batch_t *b);
+/* All items advance n sweeps with exchange every exchange_every sweeps (of
+ * the batch's common sweep counter).  Asynchronous. */
+int rfim_batch_sweep(rfim_batch_t *b, int64_t n, int exchange_every);
+int rfim_batch_synchronize(rfim_batch_t *b);
+/* Borrowed handle of item i for the observables and state calls (energies,
+ * spins, permutation, counters, statistics, save).  Owned by the batch:
+ * rfim_destroy ignores it; rfim_sweep, rfim_adapt_temps, rfim_set_counters
+ * and rfim_set_launch_shape on it return RFIM_ESTATE. */
+rfim_t *rfim_batch_item(rfim_batch_t *b, int i);
+/* Launch shape of the class (L, field_kind) (see rfim_set_launch_shape);
+ * used by the autotuner.  No effect on results. */
+int rfim_batch_set_shape(rfim_batch_t *b, int L, int field_kind, int mode, int nw, int wg);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,148 @@
+"""Launch-shape autotuner for batches.
+
+Every launch shape gives bit-identical chains, so the tuner only measures
+time.  For each class (L, field kind) of a batch it times a probe batch built
+from the same realization specs (so the real chains are not advanced) over a
+few exchange intervals per candidate shape, one class at a time with the
+others fixed, and keeps the fastest.  Results are cached in a JSON file keyed
+by (L, field kind, replicas of the class, members of the class).
+
+The paper picks its block by minimising the halo surface of a w x x x y box
+of fixed volume V (Sec. 3.2, Eq. 4-5): x = y = sqrt(V/w), giving
+B_opt = (32, 4, 8) threads for V = 2 x 1024 spins and 32-wide warps.
+`halo_optimal_block` restates that rule; it orders the candidates here (the
+closest-to-optimal thread count first) but the measurement decides.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from typing import Dict, List, Optional, Tuple
+
+from .rfim import FIELDS_BIMODAL, FIELDS_CONTINUOUS, Batch
+
+DEFAULT_CACHE = os.environ.get(
+    "RFIM_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "rfim_mi355x_tune.json"))
+
+
+def halo_optimal_block(V: int, w: int) -> Tuple[int, int, int]:
+    """Eq. 4-5: minimise S = 2(wy + xy + wx) at fixed V = wxy -> x = y =
+    sqrt(V/w).  Returns the (w, y, x) box in spins; with two spins per
+    thread (checkerboard) the thread block is (w, y/2, x)."""
+    x = math.sqrt(V / w)
+    return (w, int(round(x)), int(round(x)))
+
+
+def halo_surface(w: int, x: float, y: float) -> float:
+    return 2.0 * (w * y + x * y + w * x)
+
+
+def candidate_shapes(L: int) -> List[Tuple[int, int, int]]:
+    """Valid (mode, dwords per thread, threads per workgroup) for L."""
+    out = []
+    for nw in (1, 2, 4):
+        if 4 * nw > L // 2:
+            continue
+        chunks = L ** 3 // 8 // nw
+        for wg in (64, 128, 256):
+            if chunks % wg == 0 or chunks < wg:
+                out.append((0, nw, wg))
+        if L <= 32:
+            for wg in (64, 128, 256, 512, 1024):
+                out.append((1, nw, wg))
+    # wave64 analogue of the paper's rule: a wave covers a 64-site row
+    # segment, so order by distance of the thread count from the optimum box
+    _, y, x = halo_optimal_block(2 * 1024, 64)
+    opt = 64 * y * x // 2
+    out.sort(key=lambda s: (abs(math.log2(s[2] * 4 * s[1]) - math.log2(max(opt, 1))), s))
+    return out
+
+
+def _kind_of(w) -> int:
+    import numpy as np
+
+    fk = getattr(w, "field_kind", -1)
+    if fk in (FIELDS_BIMODAL, FIELDS_CONTINUOUS):
+        return fk
+    f = np.asarray(w.fields)
+    return FIELDS_BIMODAL if np.all((f == 1.0) | (f == -1.0)) else FIELDS_CONTINUOUS
+
+
+def class_key(L: int, kind: int, items) -> str:
+    return "L%d_k%d_R%d_n%d" % (L, kind, sum(int(w.R) for w in items), len(items))
+
+
+def load_cache(path: str = DEFAULT_CACHE) -> Dict[str, list]:
+    try:
+        with open(path) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(cache: Dict[str, list], path: str = DEFAULT_CACHE) -> None:
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+
+
+def _time_batch(torch, batch, stream, every: int, intervals: int) -> float:
+    batch.sweep(every, every)          # warm the shape (and capture its graph)
+    batch.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    batch.sweep(every * intervals, every)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def tune(specs, every: int = 10, intervals: int = 3, cache_path: Optional[str] = DEFAULT_CACHE,
+         log=None) -> Dict[Tuple[int, int], Tuple[int, int, int]]:
+    """Best shape per (L, field kind) class of the given realization specs."""
+    import torch
+
+    classes: Dict[Tuple[int, int], list] = {}
+    for w in specs:
+        classes.setdefault((int(w.L), _kind_of(w)), []).append(w)
+    cache = load_cache(cache_path) if cache_path else {}
+    best: Dict[Tuple[int, int], Tuple[int, int, int]] = {}
+    todo = []
+    for key, items in classes.items():
+        ck = class_key(key[0], key[1], items)
+        if ck in cache:
+            best[key] = tuple(cache[ck])
+        else:
+            todo.append(key)
+    if todo:
+        stream = torch.cuda.Stream()
+        probe = Batch(specs, stream=stream)
+        for key in todo:
+            L, kind = key
+            timings = []
+            for shape in candidate_shapes(L):
+                probe.set_shape(L, kind, *shape)
+                ms = _time_batch(torch, probe, stream, every, intervals)
+                timings.append((ms, shape))
+                if log:
+                    log("tune L=%d kind=%d shape %s: %.3f ms" % (L, kind, shape, ms))
+            ms, shape = min(timings)
+            best[key] = shape
+            probe.set_shape(L, kind, *shape)
+            cache[class_key(L, kind, classes[key])] = list(shape)
+        probe.close()
+        if cache_path:
+            save_cache(cache, cache_path)
+    return best
+
+
+def apply(batch: Batch, shapes: Dict[Tuple[int, int], Tuple[int, int, int]]) -> None:
+    for (L, kind), shape in shapes.items():
+        batch.set_shape(L, kind, *shape)

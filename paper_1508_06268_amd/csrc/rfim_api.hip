@@ -70,6 +70,13 @@ struct rfim {
     double *d_F = nullptr;
     int nblk = 1;
     int mode = 0, nw = 0, wg = 0;   // launch shape (see rfim_set_launch_shape)
+    // device copy of lattice() and the workgroup maps of the sweep launches
+    Lattice lat_host;
+    Lattice *d_lat = nullptr;
+    uint2 *d_smap = nullptr, *d_rmap = nullptr;
+    size_t smap_cap = 0;
+    int smap_n = 0;
+    bool in_batch = false;          // owned by a batch: no standalone launches
 
     Lattice lattice() const {
         Lattice a;
@@ -116,6 +123,9 @@ void free_device(rfim *h) {
                     h->d_acc,   h->d_ctrs,  h->d_B,   h->d_M,    h->d_F};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    if (h->d_lat) (void)hipFree(h->d_lat);
+    if (h->d_smap) (void)hipFree(h->d_smap);
+    if (h->d_rmap) (void)hipFree(h->d_rmap);
 }
 
 int validate(const rfim_params_t *p, int *kind_out) {
@@ -240,6 +250,17 @@ int alloc_device(rfim *h) {
     ALLOC(h->d_B, Rc * sizeof(int64_t));
     ALLOC(h->d_M, Rc * sizeof(int64_t));
     ALLOC(h->d_F, Rc * sizeof(double));
+    ALLOC(h->d_lat, sizeof(Lattice));
+    ALLOC(h->d_rmap, Rc * sizeof(uint2));
+    if (h->log2L >= 3) {
+        size_t maxw = 1;
+        for (int nw : {1, 2, 4})
+            for (int wg : {64, 128, 256})
+                if (rfim_dev::shape_valid(h->L, 0, nw, wg))
+                    maxw = std::max(maxw, (size_t)rfim_dev::stream_blocks_per_replica(h->L, nw, wg));
+        h->smap_cap = Rc * maxw;
+        ALLOC(h->d_smap, h->smap_cap * sizeof(uint2));
+    }
 #undef ALLOC
     (void)half;
     return RFIM_OK;
@@ -279,6 +300,41 @@ int upload_counters(rfim *h) {
     HIPCHK(hipMemcpyAsync(h->d_ctrs, c, sizeof c, hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     return RFIM_OK;
+}
+
+// Upload the descriptor and rebuild the workgroup maps for the current R
+// and launch shape (entries: (0 << 16 | replica, block)).
+int sync_descriptor(rfim *h) {
+    h->lat_host = h->lattice();
+    HIPCHK(hipMemcpyAsync(h->d_lat, &h->lat_host, sizeof(Lattice), hipMemcpyHostToDevice, h->stream));
+    std::vector<uint2> rmap(h->R);
+    for (int r = 0; r < h->R; ++r) rmap[r] = make_uint2((uint32_t)r, 0u);
+    HIPCHK(hipMemcpyAsync(h->d_rmap, rmap.data(), rmap.size() * sizeof(uint2), hipMemcpyHostToDevice, h->stream));
+    std::vector<uint2> smap;
+    if (h->log2L >= 3 && h->mode == 0) {
+        const int wpr = rfim_dev::stream_blocks_per_replica(h->L, h->nw, h->wg);
+        smap.resize((size_t)h->R * wpr);
+        for (int r = 0; r < h->R; ++r)
+            for (int b = 0; b < wpr; ++b) smap[(size_t)r * wpr + b] = make_uint2((uint32_t)r, (uint32_t)b);
+        HIPCHK(hipMemcpyAsync(h->d_smap, smap.data(), smap.size() * sizeof(uint2), hipMemcpyHostToDevice, h->stream));
+    }
+    h->smap_n = (int)smap.size();
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return RFIM_OK;
+}
+
+rfim_dev::Launch single_launch(const rfim *h) {
+    rfim_dev::Launch ln;
+    ln.single = &h->lat_host;
+    ln.lats = h->d_lat;
+    ln.map = h->mode == 1 ? h->d_rmap : h->d_smap;
+    ln.nblocks = h->mode == 1 ? h->R : h->smap_n;
+    ln.L = h->L;
+    ln.kind = h->kind;
+    ln.mode = h->mode;
+    ln.nw = h->nw;
+    ln.wg = h->wg;
+    return ln;
 }
 
 int reset_stats(rfim *h) {
@@ -373,6 +429,7 @@ int init_device(rfim *h) {
     if ((rc = upload_perm(h, ident))) return rc;
     if ((rc = upload_counters(h))) return rc;
     if ((rc = reset_stats(h))) return rc;
+    if ((rc = sync_descriptor(h))) return rc;
     HIPCHK(rfim_dev::launch_init(h->lattice(), 0, h->R, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     return RFIM_OK;
@@ -387,24 +444,32 @@ void destroy_impl(rfim *h) {
 }
 
 int sweep_impl(rfim *h, int64_t n, int every) {
-    Lattice lat = h->lattice();
+    h->lat_host = h->lattice();
+    const Lattice &lat = h->lat_host;
+    const rfim_dev::Launch ln = single_launch(h);
+    const bool pow2 = h->log2L >= 3;
     int64_t remaining = n;
     while (remaining > 0) {
         int64_t to_next = every > 0 ? (int64_t)(every - (int64_t)(h->t % (uint64_t)every)) : remaining;
         const int m = (int)std::min<int64_t>(remaining, to_next);
         const bool exch = every > 0 && m == to_next;
         const bool fused = exch && rfim_dev::fused_energy(lat);
-        if (h->mode == 1) {
-            HIPCHK(rfim_dev::launch_resident(lat, m, fused ? 1 : 0, h->stream));
+        if (pow2 && h->mode == 1) {
+            HIPCHK(rfim_dev::launch_resident(ln, m, fused ? 1 : 0, h->stream));
+        } else if (pow2) {
+            for (int q = 0; q < m; ++q) {
+                HIPCHK(rfim_dev::launch_stream_sweep(ln, 0, q, 0, h->stream));
+                HIPCHK(rfim_dev::launch_stream_sweep(ln, 1, q, fused && q == m - 1, h->stream));
+            }
         } else {
             for (int q = 0; q < m; ++q) {
-                HIPCHK(rfim_dev::launch_sweep(lat, 0, q, 0, h->stream));
-                HIPCHK(rfim_dev::launch_sweep(lat, 1, q, fused && q == m - 1, h->stream));
+                HIPCHK(rfim_dev::launch_generic_sweep(lat, 0, q, h->stream));
+                HIPCHK(rfim_dev::launch_generic_sweep(lat, 1, q, h->stream));
             }
         }
         if (exch) {
             if (!fused) HIPCHK(rfim_dev::launch_energy(lat, h->stream));
-            HIPCHK(rfim_dev::launch_exchange(lat, m, h->stream));
+            HIPCHK(rfim_dev::launch_exchange(h->d_lat, 1, m, h->stream));
             h->k += 1;
         } else {
             HIPCHK(rfim_dev::launch_advance(lat, m, h->stream));
@@ -454,7 +519,10 @@ rfim_t *rfim_create(int L, int R, double J, double h, const float *fields, const
     return rfim_create_ex(&p, nullptr);
 }
 
-void rfim_destroy(rfim_t *h) { destroy_impl(h); }
+void rfim_destroy(rfim_t *h) {
+    if (h && h->in_batch) return;   // owned by its batch
+    destroy_impl(h);
+}
 
 int rfim_set_stream(rfim_t *h, void *hip_stream) {
     if (!h) return fail(RFIM_EINVAL, "handle is NULL");
@@ -480,6 +548,7 @@ int rfim_synchronize(rfim_t *h) {
 
 int rfim_sweep(rfim_t *h, int64_t n, int exchange_every) {
     if (!h) return fail(RFIM_EINVAL, "handle is NULL");
+    if (h->in_batch) return fail(RFIM_ESTATE, "batch items advance through rfim_batch_sweep");
     if (n < 0 || exchange_every < 0) return fail(RFIM_EINVAL, "n and exchange_every must be >= 0");
     if (h->t + (uint64_t)n > kMaxSweeps) return fail(RFIM_ECAP, "global sweep counter would pass 2^31-1");
     return sweep_impl(h, n, exchange_every);
@@ -593,6 +662,7 @@ int rfim_get_counters(rfim_t *h, uint64_t *t, uint64_t *k) {
 
 int rfim_set_counters(rfim_t *h, uint64_t t, uint64_t k) {
     if (!h) return fail(RFIM_EINVAL, "handle is NULL");
+    if (h->in_batch) return fail(RFIM_ESTATE, "batch items share the batch's counters");
     if (t > kMaxSweeps || k > 0xFFFFFFFFull) return fail(RFIM_ECAP, "counter beyond its range");
     HIPCHK(hipStreamSynchronize(h->stream));
     h->t = t;
@@ -620,6 +690,7 @@ int rfim_adapt_temps(rfim_t *h, int trials, int64_t sweeps_per_trial, int exchan
     if (trials < 0 || sweeps_per_trial < 0 || exchange_every <= 0 || max_insert_per_trial < 0 ||
         std::isnan(rate_threshold))
         return fail(RFIM_EINVAL, "bad adapt arguments");
+    if (h->in_batch) return fail(RFIM_ESTATE, "batch items cannot change R");
     if (R_cap > h->R_cap) return fail(RFIM_ECAP, "R_cap %d beyond the capacity %d given at create", R_cap, h->R_cap);
     if (h->t + (uint64_t)trials * (uint64_t)sweeps_per_trial > kMaxSweeps)
         return fail(RFIM_ECAP, "global sweep counter would pass 2^31-1");
@@ -675,6 +746,7 @@ int rfim_adapt_temps(rfim_t *h, int trials, int64_t sweeps_per_trial, int exchan
         }
         if ((rc = upload_perm(h, nt2r))) return rc;
         if ((rc = upload_tables(h))) return rc;
+        if ((rc = sync_descriptor(h))) return rc;
         if ((rc = reset_stats(h))) return rc;
     }
     HIPCHK(hipStreamSynchronize(h->stream));
@@ -683,6 +755,7 @@ int rfim_adapt_temps(rfim_t *h, int trials, int64_t sweeps_per_trial, int exchan
 
 int rfim_set_launch_shape(rfim_t *h, int mode, int nw, int wg) {
     if (!h) return fail(RFIM_EINVAL, "handle is NULL");
+    if (h->in_batch) return fail(RFIM_ESTATE, "batch items take their class shape (rfim_batch_set_shape)");
     if (!rfim_dev::shape_valid(h->L, mode, nw, wg))
         return fail(RFIM_EINVAL, "launch shape (%d, %d, %d) not valid for L=%d", mode, nw, wg, h->L);
     HIPCHK(hipStreamSynchronize(h->stream));
@@ -690,7 +763,7 @@ int rfim_set_launch_shape(rfim_t *h, int mode, int nw, int wg) {
     h->nw = nw;
     h->wg = wg;
     h->nblk = rfim_dev::blocks_per_replica(h->L, mode, nw, wg);
-    return RFIM_OK;
+    return sync_descriptor(h);
 }
 
 int rfim_get_launch_shape(const rfim_t *h, int *mode, int *nw, int *wg) {
@@ -820,6 +893,309 @@ rfim_t *rfim_load(const void *buf, size_t len, void *hip_stream) {
         return nullptr;
     }
     return h;
+}
+
+}  // extern "C"
+
+// ===================================================================
+// Batches: many independent realizations advanced together.  The sweeps of
+// every realization that shares (L, field kind) go into one launch per
+// half-sweep (streaming) or per exchange interval (LDS-resident), and one
+// launch runs the exchange step of every realization; a full exchange
+// interval is captured once in a HIP graph and replayed.
+// ===================================================================
+struct rfim_batch {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<rfim *> items;
+    Lattice *d_lats = nullptr;
+    std::vector<Lattice> lats_host;
+    struct Class {
+        int L = 0, kind = 0, mode = 0, nw = 0, wg = 0;
+        std::vector<int> members;
+        uint2 *d_map = nullptr;
+        int nblocks = 0;
+    };
+    std::vector<Class> classes;
+    uint64_t t = 0, k = 0;
+    hipGraphExec_t graph = nullptr;
+    int graph_every = 0;
+};
+
+namespace {
+
+void batch_free(rfim_batch *b) {
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    for (auto &c : b->classes)
+        if (c.d_map) (void)hipFree(c.d_map);
+    if (b->d_lats) (void)hipFree(b->d_lats);
+    for (rfim *h : b->items) {
+        h->stream = nullptr;      // the batch owns the stream
+        h->own_stream = false;
+        free_device(h);
+        delete h;
+    }
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+// Descriptors of every item and the workgroup maps of every class.
+int batch_build(rfim_batch *b) {
+    const int n = (int)b->items.size();
+    b->lats_host.resize(n);
+    for (int i = 0; i < n; ++i) b->lats_host[i] = b->items[i]->lattice();
+    HIPCHK(hipMemcpyAsync(b->d_lats, b->lats_host.data(), n * sizeof(Lattice), hipMemcpyHostToDevice, b->stream));
+    std::vector<std::vector<uint2>> maps(b->classes.size());
+    for (size_t ci = 0; ci < b->classes.size(); ++ci) {
+        auto &c = b->classes[ci];
+        std::vector<uint2> &map = maps[ci];
+        for (int i : c.members) {
+            const rfim *h = b->items[i];
+            const uint32_t hi = (uint32_t)i << 16;
+            if (c.mode == 1) {
+                for (int r = 0; r < h->R; ++r) map.push_back(make_uint2(hi | (uint32_t)r, 0u));
+            } else {
+                const int wpr = rfim_dev::stream_blocks_per_replica(c.L, c.nw, c.wg);
+                for (int r = 0; r < h->R; ++r)
+                    for (int g = 0; g < wpr; ++g) map.push_back(make_uint2(hi | (uint32_t)r, (uint32_t)g));
+            }
+        }
+        if (c.d_map) HIPCHK(hipFree(c.d_map));
+        c.d_map = nullptr;
+        c.nblocks = (int)map.size();
+        if (!map.empty()) {
+            hipError_t e = hipMalloc((void **)&c.d_map, map.size() * sizeof(uint2));
+            if (e != hipSuccess) return fail(RFIM_ENOMEM, "hipMalloc(batch map): %s", hipGetErrorString(e));
+            HIPCHK(hipMemcpyAsync(c.d_map, map.data(), map.size() * sizeof(uint2), hipMemcpyHostToDevice, b->stream));
+        }
+    }
+    HIPCHK(hipStreamSynchronize(b->stream));
+    if (b->graph) {
+        HIPCHK(hipGraphExecDestroy(b->graph));
+        b->graph = nullptr;
+        b->graph_every = 0;
+    }
+    return RFIM_OK;
+}
+
+rfim_dev::Launch class_launch(const rfim_batch *b, const rfim_batch::Class &c) {
+    rfim_dev::Launch ln;
+    ln.single = nullptr;
+    ln.lats = b->d_lats;
+    ln.map = c.d_map;
+    ln.nblocks = c.nblocks;
+    ln.L = c.L;
+    ln.kind = c.kind;
+    ln.mode = c.mode;
+    ln.nw = c.nw;
+    ln.wg = c.wg;
+    return ln;
+}
+
+// m sweeps of every item; exch: energies (fused) and one exchange step.
+int batch_segment(rfim_batch *b, int m, bool exch) {
+    for (const auto &c : b->classes) {
+        const rfim_dev::Launch ln = class_launch(b, c);
+        if (c.mode == 1) {
+            HIPCHK(rfim_dev::launch_resident(ln, m, exch ? 1 : 0, b->stream));
+        } else {
+            for (int q = 0; q < m; ++q) {
+                HIPCHK(rfim_dev::launch_stream_sweep(ln, 0, q, 0, b->stream));
+                HIPCHK(rfim_dev::launch_stream_sweep(ln, 1, q, exch && q == m - 1, b->stream));
+            }
+        }
+    }
+    if (exch) {
+        HIPCHK(rfim_dev::launch_exchange(b->d_lats, (int)b->items.size(), m, b->stream));
+    } else {
+        for (rfim *h : b->items) HIPCHK(rfim_dev::launch_advance(h->lattice(), m, b->stream));
+    }
+    return RFIM_OK;
+}
+
+int batch_capture(rfim_batch *b, int every) {
+    if (b->graph) {
+        HIPCHK(hipGraphExecDestroy(b->graph));
+        b->graph = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    int rc = batch_segment(b, every, true);
+    hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(RFIM_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(RFIM_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    b->graph_every = every;
+    return RFIM_OK;
+}
+
+void note_advance(rfim_batch *b, int m, bool exch) {
+    b->t += (uint64_t)m;
+    if (exch) b->k += 1;
+    for (rfim *h : b->items) {
+        h->t = b->t;
+        h->k = b->k;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+rfim_batch_t *rfim_batch_create(int n, const rfim_params_t *items, void *hip_stream) {
+    if (n < 1 || n > 65536 || !items) {
+        fail(RFIM_EINVAL, "need 1 <= n <= 65536 items");
+        return nullptr;
+    }
+    for (int i = 0; i < n; ++i) {
+        int kind;
+        if (validate(&items[i], &kind)) {
+            std::string msg = g_error;
+            fail(RFIM_EINVAL, "item %d: %s", i, msg.c_str());
+            return nullptr;
+        }
+        const int L = items[i].L;
+        if (!(L >= 8 && (L & (L - 1)) == 0)) {
+            fail(RFIM_EINVAL, "item %d: batches need L a power of two >= 8 (got %d)", i, L);
+            return nullptr;
+        }
+    }
+    rfim_batch *b = new (std::nothrow) rfim_batch();
+    if (!b) {
+        fail(RFIM_ENOMEM, "out of host memory");
+        return nullptr;
+    }
+    if (hip_stream) {
+        b->stream = (hipStream_t)hip_stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            fail(RFIM_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+            delete b;
+            return nullptr;
+        }
+        b->own_stream = true;
+    }
+    for (int i = 0; i < n; ++i) {
+        int err = 0;
+        rfim *h = create_impl(&items[i], b->stream, &err);
+        if (!h) {
+            batch_free(b);
+            return nullptr;
+        }
+        h->in_batch = true;
+        b->items.push_back(h);
+        if (init_device(h)) {
+            std::string msg = g_error;
+            batch_free(b);
+            fail(RFIM_ENOMEM, "item %d: %s", i, msg.c_str());
+            return nullptr;
+        }
+        // one class per (L, field kind), default shape of the class
+        int ci = -1;
+        for (size_t c = 0; c < b->classes.size(); ++c)
+            if (b->classes[c].L == h->L && b->classes[c].kind == h->kind) ci = (int)c;
+        if (ci < 0) {
+            rfim_batch::Class c;
+            c.L = h->L;
+            c.kind = h->kind;
+            c.mode = h->mode;
+            c.nw = h->nw;
+            c.wg = h->wg;
+            b->classes.push_back(c);
+            ci = (int)b->classes.size() - 1;
+        }
+        auto &c = b->classes[ci];
+        c.members.push_back(i);
+        h->mode = c.mode;
+        h->nw = c.nw;
+        h->wg = c.wg;
+        h->nblk = rfim_dev::blocks_per_replica(h->L, c.mode, c.nw, c.wg);
+    }
+    hipError_t e = hipMalloc((void **)&b->d_lats, n * sizeof(Lattice));
+    if (e != hipSuccess) {
+        batch_free(b);
+        fail(RFIM_ENOMEM, "hipMalloc(batch descriptors): %s", hipGetErrorString(e));
+        return nullptr;
+    }
+    if (batch_build(b)) {
+        std::string msg = g_error;
+        batch_free(b);
+        g_error = msg;
+        return nullptr;
+    }
+    return b;
+}
+
+void rfim_batch_destroy(rfim_batch_t *b) { batch_free(b); }
+
+int rfim_batch_size(const rfim_batch_t *b) { return b ? (int)b->items.size() : fail(RFIM_EINVAL, "batch is NULL"); }
+
+rfim_t *rfim_batch_item(rfim_batch_t *b, int i) {
+    if (!b || i < 0 || i >= (int)b->items.size()) {
+        fail(RFIM_EINVAL, "no such batch item");
+        return nullptr;
+    }
+    return b->items[i];
+}
+
+int rfim_batch_set_shape(rfim_batch_t *b, int L, int field_kind, int mode, int nw, int wg) {
+    if (!b) return fail(RFIM_EINVAL, "batch is NULL");
+    if (!rfim_dev::shape_valid(L, mode, nw, wg))
+        return fail(RFIM_EINVAL, "launch shape (%d, %d, %d) not valid for L=%d", mode, nw, wg, L);
+    HIPCHK(hipStreamSynchronize(b->stream));
+    for (auto &c : b->classes) {
+        if (c.L != L || c.kind != field_kind) continue;
+        c.mode = mode;
+        c.nw = nw;
+        c.wg = wg;
+        for (int i : c.members) {
+            rfim *h = b->items[i];
+            h->mode = mode;
+            h->nw = nw;
+            h->wg = wg;
+            h->nblk = rfim_dev::blocks_per_replica(h->L, mode, nw, wg);
+            int rc = sync_descriptor(h);
+            if (rc) return rc;
+        }
+    }
+    return batch_build(b);
+}
+
+int rfim_batch_sweep(rfim_batch_t *b, int64_t n, int exchange_every) {
+    if (!b) return fail(RFIM_EINVAL, "batch is NULL");
+    if (n < 0 || exchange_every < 0) return fail(RFIM_EINVAL, "n and exchange_every must be >= 0");
+    if (b->t + (uint64_t)n > kMaxSweeps) return fail(RFIM_ECAP, "global sweep counter would pass 2^31-1");
+    int64_t remaining = n;
+    const int every = exchange_every;
+    while (remaining > 0) {
+        const int64_t to_next = every > 0 ? (int64_t)(every - (int64_t)(b->t % (uint64_t)every)) : remaining;
+        const int m = (int)std::min<int64_t>(remaining, to_next);
+        const bool exch = every > 0 && m == to_next;
+        int rc;
+        if (exch && m == every) {
+            if (b->graph_every != every && (rc = batch_capture(b, every))) return rc;
+            HIPCHK(hipGraphLaunch(b->graph, b->stream));
+        } else if ((rc = batch_segment(b, m, exch))) {
+            return rc;
+        }
+        note_advance(b, m, exch);
+        remaining -= m;
+    }
+    return RFIM_OK;
+}
+
+int rfim_batch_synchronize(rfim_batch_t *b) {
+    if (!b) return fail(RFIM_EINVAL, "batch is NULL");
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return RFIM_OK;
 }
 
 }  // extern "C"

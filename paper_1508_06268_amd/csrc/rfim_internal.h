@@ -59,20 +59,41 @@ constexpr int kMaxFusedBlocks = 1024;
 // exchange interval).  Other L: generic kernel, shape (0, 0, 0).  Every
 // shape gives bit-identical results.
 bool shape_valid(int L, int mode, int nw, int wg);
+// Energy partials per replica for a shape (1 for resident, the workgroups
+// per replica when the streaming sweep fuses the energy, else 64).
 int blocks_per_replica(int L, int mode, int nw, int wg);
+// Workgroups per replica of one streaming half-sweep launch.
+int stream_blocks_per_replica(int L, int nw, int wg);
+// True when the sweep kernels themselves write the energy partials.
+bool fused_energy(const Lattice &lat);
+
+// One launch over a set of realizations that share L, field kind and shape:
+// lats = device array of descriptors; map = one entry per workgroup:
+// x = (realization << 16) | replica, y = block within the replica
+// (streaming) or 0 (resident).
+struct Launch {
+    const Lattice *lats;
+    const uint2 *map;
+    int nblocks;
+    int L, kind, mode, nw, wg;
+    // one realization: its descriptor, passed by value (lats and map
+    // unused; blocks enumerate (replica, block) in order)
+    const Lattice *single = nullptr;
+};
 
 hipError_t launch_init(const Lattice &lat, int r0, int r1, hipStream_t s);
-// energy != 0 on a colour-1 launch of a power-of-two lattice also writes
-// the energy partials of the final state (see fused_energy()).
-hipError_t launch_sweep(const Lattice &lat, int colour, int toff, int energy, hipStream_t s);
-// True when the sweep kernel itself writes the energy partials.
-bool fused_energy(const Lattice &lat);
-// mode 1: nsweep whole sweeps of every replica in one launch (energy != 0:
-// also the energy partials of the final state).
-hipError_t launch_resident(const Lattice &lat, int nsweep, int energy, hipStream_t s);
+// Streaming half-sweep of colour `colour` at sweep t + toff (power-of-two
+// L); energy != 0 on colour 1 also writes the energy partials.
+hipError_t launch_stream_sweep(const Launch &ln, int colour, int toff, int energy, hipStream_t s);
+// Resident: nsweep whole sweeps in one launch (energy != 0: also the
+// energy partials of the final state).
+hipError_t launch_resident(const Launch &ln, int nsweep, int energy, hipStream_t s);
+// Any even L, one realization.
+hipError_t launch_generic_sweep(const Lattice &lat, int colour, int toff, hipStream_t s);
 hipError_t launch_energy(const Lattice &lat, hipStream_t s);
 hipError_t launch_reduce(const Lattice &lat, int64_t *B, double *F, int64_t *M, hipStream_t s);
-hipError_t launch_exchange(const Lattice &lat, int tadv, hipStream_t s);
+// One exchange step for each of the n realizations in lats (device array).
+hipError_t launch_exchange(const Lattice *lats, int n, int tadv, hipStream_t s);
 hipError_t launch_advance(const Lattice &lat, int tadv, hipStream_t s);
 
 }  // namespace rfim_dev

@@ -16,6 +16,25 @@ namespace {
 
 constexpr uint32_t kTagInit = 1u, kTagSweep = 2u, kTagExch = 3u;
 
+// Pointers read from a descriptor table in memory are generic; typing them
+// as global (address space 1) all the way to the access keeps loads and
+// stores global_* rather than flat_* instructions.
+#define GAS __attribute__((address_space(1)))
+
+template <class T>
+__device__ __forceinline__ GAS T *gptr(T *p) {
+    return (GAS T *)p;
+}
+
+// Pointer to U in the address space (and constness) of pointer type P.
+template <class P, class U> struct rebind_ptr;
+template <class U> struct rebind_ptr<uint8_t *, U> { using type = U *; };
+template <class U> struct rebind_ptr<const uint8_t *, U> { using type = const U *; };
+template <class U> struct rebind_ptr<GAS uint8_t *, U> { using type = GAS U *; };
+template <class U> struct rebind_ptr<GAS const uint8_t *, U> { using type = GAS const U *; };
+template <class U> struct rebind_ptr<const float *, U> { using type = const U *; };
+template <class U> struct rebind_ptr<GAS const float *, U> { using type = GAS const U *; };
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, each two
 // 32x32->64 products by fixed odd multipliers whose high halves are mixed
 // with the other two words and the round key; the key follows a Weyl
@@ -143,14 +162,17 @@ __global__ __launch_bounds__(256) void sweep_generic(Lattice lat, int colour, in
 // from the adjacent dword, wrapping in the row) supply the second x
 // neighbour.
 // ---------------------------------------------------------------------
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 template <int NW> struct Vec;
 template <> struct Vec<1> { using T = uint32_t; };
-template <> struct Vec<2> { using T = uint2; };
-template <> struct Vec<4> { using T = uint4; };
+template <> struct Vec<2> { using T = u32x2; };
+template <> struct Vec<4> { using T = u32x4; };
 
-template <int NW>
-__device__ __forceinline__ void load_words(const uint8_t *base, uint32_t off, uint32_t (&w)[NW]) {
-    const typename Vec<NW>::T v = *(const typename Vec<NW>::T *)(base + off);
+template <int NW, class P>
+__device__ __forceinline__ void load_words(P base, uint32_t off, uint32_t (&w)[NW]) {
+    const typename Vec<NW>::T v = *(typename rebind_ptr<P, const typename Vec<NW>::T>::type)(base + off);
     if constexpr (NW == 1) {
         w[0] = v;
     } else if constexpr (NW == 2) {
@@ -160,8 +182,8 @@ __device__ __forceinline__ void load_words(const uint8_t *base, uint32_t off, ui
     }
 }
 
-template <int NW>
-__device__ __forceinline__ void store_words(uint8_t *base, uint32_t off, const uint32_t (&w)[NW]) {
+template <int NW, class P>
+__device__ __forceinline__ void store_words(P base, uint32_t off, const uint32_t (&w)[NW]) {
     typename Vec<NW>::T v;
     if constexpr (NW == 1) {
         v = w[0];
@@ -170,7 +192,7 @@ __device__ __forceinline__ void store_words(uint8_t *base, uint32_t off, const u
     } else {
         v.x = w[0]; v.y = w[1]; v.z = w[2]; v.w = w[3];
     }
-    *(typename Vec<NW>::T *)(base + off) = v;
+    *(typename rebind_ptr<P, typename Vec<NW>::T>::type)(base + off) = v;
 }
 
 __device__ __forceinline__ int wave_isum(int v) {
@@ -212,12 +234,12 @@ __device__ __forceinline__ Chunk chunk_geometry(uint32_t j0, uint32_t colour, ui
 }
 
 // Up-neighbour counts (per byte) of the NW words of a chunk.
-template <int NW>
-__device__ __forceinline__ void neighbour_counts(const uint8_t *oth, uint32_t j0, const Chunk &c,
-                                                 uint32_t (&W)[NW], uint32_t (&U)[NW]) {
+template <int NW, class P>
+__device__ __forceinline__ void neighbour_counts(P oth, uint32_t j0, const Chunk &c, uint32_t (&W)[NW],
+                                                 uint32_t (&U)[NW]) {
     uint32_t Wyp[NW], Wym[NW], Wzp[NW], Wzm[NW];
     load_words<NW>(oth, j0, W);
-    const uint32_t Wx = *(const uint32_t *)(oth + c.jxw);
+    const uint32_t Wx = *(typename rebind_ptr<P, const uint32_t>::type)(oth + c.jxw);
     load_words<NW>(oth, c.jyp, Wyp);
     load_words<NW>(oth, c.jym, Wym);
     load_words<NW>(oth, c.jzp, Wzp);
@@ -256,7 +278,7 @@ __device__ __forceinline__ uint32_t bimodal_flips(const uint32_t *sthr, uint32_t
 }
 
 // Continuous fields: dE = 2 s (J n + h h_i) and exp(-beta dE) in FP32.
-__device__ __forceinline__ uint32_t continuous_flips(uint32_t U, uint32_t Wown, const float4 hf, float Jf,
+__device__ __forceinline__ uint32_t continuous_flips(uint32_t U, uint32_t Wown, const f32x4 hf, float Jf,
                                                      float beta, const Words &rw) {
     const float hv[4] = {hf.x, hf.y, hf.z, hf.w};
     uint32_t fl = 0;
@@ -275,10 +297,9 @@ __device__ __forceinline__ uint32_t continuous_flips(uint32_t U, uint32_t Wown, 
 
 // One chunk's half-sweep update; returns the new own words (and the loaded
 // words the energy pass reuses).
-template <int KIND, int NW>
-__device__ __forceinline__ uint32_t chunk_update(const Lattice &lat, const uint32_t *sthr, uint8_t *own,
-                                                 const uint8_t *oth, const uint8_t *fb_own,
-                                                 const float *hf_own, uint32_t j0, uint32_t g0,
+template <int KIND, int NW, class PO, class PC, class PB, class PF>
+__device__ __forceinline__ uint32_t chunk_update(const Lattice &lat, const uint32_t *sthr, PO own, PC oth,
+                                                 PB fb_own, PF hf_own, uint32_t j0, uint32_t g0,
                                                  uint32_t colour, uint32_t c1, uint32_t r, float beta,
                                                  uint32_t (&W)[NW], uint32_t (&U)[NW],
                                                  uint32_t (&Wnew)[NW], uint32_t (&F4)[NW]) {
@@ -296,7 +317,7 @@ __device__ __forceinline__ uint32_t chunk_update(const Lattice &lat, const uint3
         if (KIND == 0) {
             fl = bimodal_flips(sthr, U[w], Wown[w], F4[w], rw, lat.always_mask);
         } else {
-            const float4 hf = *(const float4 *)(hf_own + j0 + 4u * w);
+            const f32x4 hf = *(typename rebind_ptr<PF, const f32x4>::type)(hf_own + j0 + 4u * w);
             fl = continuous_flips(U[w], Wown[w], hf, lat.Jf, beta, rw);
         }
         any |= fl;
@@ -309,11 +330,10 @@ __device__ __forceinline__ uint32_t chunk_update(const Lattice &lat, const uint3
 // same pairs, from the final spins: every bond joins a colour-0 and a
 // colour-1 site, so B = sum over colour-1 sites of s_i n_i counts each bond
 // once; F and M take both colours.
-template <int KIND, int NW>
+template <int KIND, int NW, class PB, class PF>
 __device__ __forceinline__ void chunk_energy(const Lattice &lat, const uint32_t (&S1)[NW],
                                              const uint32_t (&S0)[NW], const uint32_t (&U)[NW],
-                                             const uint32_t (&F1)[NW], const uint8_t *fb0,
-                                             const float *fr1, const float *fr0, uint32_t j0,
+                                             const uint32_t (&F1)[NW], PB fb0, PF fr1, PF fr0, uint32_t j0,
                                              int &ksum, int &upsum, int &eqsum, double &fsum) {
     uint32_t F0[NW];
     if (KIND == 0) load_words<NW>(fb0, j0, F0);
@@ -328,8 +348,8 @@ __device__ __forceinline__ void chunk_energy(const Lattice &lat, const uint32_t 
             const uint32_t e0 = ~(S0[w] ^ (F0[w] >> 2)) & 0x01010101u;
             eqsum = (int)__builtin_amdgcn_sad_u8(e1 + e0, 0u, (uint32_t)eqsum);
         } else {
-            const float4 f1 = *(const float4 *)(fr1 + j0 + 4u * w);
-            const float4 f0 = *(const float4 *)(fr0 + j0 + 4u * w);
+            const f32x4 f1 = *(typename rebind_ptr<PF, const f32x4>::type)(fr1 + j0 + 4u * w);
+            const f32x4 f0 = *(typename rebind_ptr<PF, const f32x4>::type)(fr0 + j0 + 4u * w);
             const float a1[4] = {f1.x, f1.y, f1.z, f1.w}, a0[4] = {f0.x, f0.y, f0.z, f0.w};
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -341,8 +361,8 @@ __device__ __forceinline__ void chunk_energy(const Lattice &lat, const uint32_t 
 }
 
 // Block-wide (B, F, M) partial in a fixed order; thread 0..2 write it.
-template <int KIND>
-__device__ __forceinline__ void block_partial(double *dst, int nsite, int ksum, int upsum, int eqsum,
+template <int KIND, class PD>
+__device__ __forceinline__ void block_partial(PD dst, int nsite, int ksum, int upsum, int eqsum,
                                               double fsum) {
     __shared__ double red[3][16];
     const int bpart = 2 * ksum - 6 * nsite;
@@ -365,12 +385,14 @@ __device__ __forceinline__ void block_partial(double *dst, int nsite, int ksum, 
     }
 }
 
-// Streaming half-sweep: one chunk per thread, all replicas in one launch.
-// ENERGY (colour 1 of the last sweep before an exchange) also writes one
-// energy partial per workgroup.
-template <int KIND, int NW, int ENERGY>
-__global__ __launch_bounds__(256) void sweep_pow2(Lattice lat, int colour, int toff, int wg_per_rep,
-                                                   int remap) {
+// Streaming half-sweep: one chunk per thread; one launch covers every
+// replica of every realization listed in the block map (entry: realization,
+// (replica << 16) | block within the replica).  ENERGY (colour 1 of the last
+// sweep before an exchange) also writes one energy partial per workgroup.
+template <int KIND, int NW, int ENERGY, bool BATCH>
+__global__ __launch_bounds__(256) void sweep_pow2(Lattice lat0, const Lattice *__restrict__ lats,
+                                                   const uint2 *__restrict__ map, int colour, int toff,
+                                                   int remap, int wpr) {
     __shared__ uint32_t sthr[32];
     uint32_t blk = blockIdx.x;
     if (remap) {
@@ -379,33 +401,43 @@ __global__ __launch_bounds__(256) void sweep_pow2(Lattice lat, int colour, int t
         const uint32_t per = gridDim.x >> 3;
         blk = (blk & 7u) * per + (blk >> 3);
     }
-    const uint32_t r = blk / (uint32_t)wg_per_rep;
-    const uint32_t gb = blk - r * (uint32_t)wg_per_rep;
-    const int slot = lat.r2t[r];
+    uint32_t r, gb;
+    if (BATCH) {
+        const uint2 e = map[blk];
+        r = e.x & 0xFFFFu;
+        gb = e.y;
+    } else {
+        r = blk / (uint32_t)wpr;
+        gb = blk - r * (uint32_t)wpr;
+    }
+    const Lattice &lat = BATCH ? lats[map[blk].x >> 16] : lat0;
+    const int slot = gptr(lat.r2t)[r];
     if (KIND == 0) {
-        if (threadIdx.x < 32) sthr[threadIdx.x] = lat.thr[slot * 32 + threadIdx.x];
+        if (threadIdx.x < 32) sthr[threadIdx.x] = gptr(lat.thr)[slot * 32 + threadIdx.x];
         __syncthreads();
     }
     const uint32_t g0 = (gb * blockDim.x + threadIdx.x) * NW;   // first Philox block
     const uint32_t j0 = 4u * g0;
     const uint32_t col = (uint32_t)colour;
-    uint8_t *own = lat.spins + (size_t)r * lat.N + (size_t)col * lat.half;
-    const uint8_t *oth = lat.spins + (size_t)r * lat.N + (size_t)(1 - col) * lat.half;
-    const uint32_t t = (uint32_t)(lat.ctrs[0] + (uint64_t)toff);
-    const float beta = KIND == 1 ? lat.betaf[slot] : 0.0f;
+    GAS uint8_t *spins = gptr(lat.spins);
+    GAS uint8_t *own = spins + (size_t)r * lat.N + (size_t)col * lat.half;
+    GAS const uint8_t *oth = spins + (size_t)r * lat.N + (size_t)(1 - col) * lat.half;
+    GAS const uint8_t *fbits = gptr(lat.fbits);
+    GAS const float *fhf = gptr(lat.fhf), *fraw = gptr(lat.fraw);
+    const uint32_t t = (uint32_t)(gptr(lat.ctrs)[0] + (uint64_t)toff);
+    const float beta = KIND == 1 ? gptr(lat.betaf)[slot] : 0.0f;
     uint32_t W[NW], U[NW], Wnew[NW], F4[NW];
-    const uint32_t any = chunk_update<KIND, NW>(
-        lat, sthr, own, oth, KIND == 0 ? lat.fbits + (size_t)col * lat.half : nullptr,
-        KIND == 1 ? lat.fhf + (size_t)col * lat.half : nullptr, j0, g0, col, 2u * t + col, r, beta, W, U,
-        Wnew, F4);
+    const uint32_t any = chunk_update<KIND, NW>(lat, sthr, own, oth, fbits + (size_t)col * lat.half,
+                                                fhf + (size_t)col * lat.half, j0, g0, col, 2u * t + col, r,
+                                                beta, W, U, Wnew, F4);
     if (any) store_words<NW>(own, j0, Wnew);
     if (ENERGY) {
         int ksum = 0, upsum = 0, eqsum = 0;
         double fsum = 0.0;
-        chunk_energy<KIND, NW>(lat, Wnew, W, U, F4, KIND == 0 ? lat.fbits : nullptr,
-                               KIND == 1 ? lat.fraw + lat.half : nullptr, KIND == 1 ? lat.fraw : nullptr,
-                               j0, ksum, upsum, eqsum, fsum);
-        block_partial<KIND>(lat.part + ((size_t)r * lat.nblk + gb) * 3, 4 * NW, ksum, upsum, eqsum, fsum);
+        chunk_energy<KIND, NW>(lat, Wnew, W, U, F4, fbits, fraw + lat.half, fraw, j0, ksum, upsum, eqsum,
+                               fsum);
+        block_partial<KIND>(gptr(lat.part) + ((size_t)r * lat.nblk + gb) * 3, 4 * NW, ksum, upsum, eqsum,
+                            fsum);
     }
 }
 
@@ -414,19 +446,26 @@ __global__ __launch_bounds__(256) void sweep_pow2(Lattice lat, int colour, int t
 // between half-sweeps), then, if asked, the energy partial of the final
 // state, and writes the spins back.  Fields stay in global memory (shared
 // by every replica, so they live in L2).
-template <int KIND, int NW>
-__global__ __launch_bounds__(1024) void sweep_resident(Lattice lat, int nsweep, int energy) {
+template <int KIND, int NW, bool BATCH>
+__global__ __launch_bounds__(1024) void sweep_resident(Lattice lat0, const Lattice *__restrict__ lats,
+                                                        const uint2 *__restrict__ map, int nsweep,
+                                                        int energy) {
     extern __shared__ uint4 lds_raw[];
     __shared__ uint32_t sthr[32];
     uint8_t *sp = (uint8_t *)lds_raw;                  // [2][half]
-    const uint32_t r = blockIdx.x;
+    // batch: map entry (realization << 16 | replica, 0)
+    const Lattice &lat = BATCH ? lats[map[blockIdx.x].x >> 16] : lat0;
+    const uint32_t r = BATCH ? (map[blockIdx.x].x & 0xFFFFu) : blockIdx.x;
     const uint32_t N = (uint32_t)lat.N, half = (uint32_t)lat.half;
-    const int slot = lat.r2t[r];
-    const uint4 *src = (const uint4 *)(lat.spins + (size_t)r * N);
-    for (uint32_t q = threadIdx.x; q < N / 16u; q += blockDim.x) lds_raw[q] = src[q];
-    if (KIND == 0 && threadIdx.x < 32) sthr[threadIdx.x] = lat.thr[slot * 32 + threadIdx.x];
-    const float beta = KIND == 1 ? lat.betaf[slot] : 0.0f;
-    const uint32_t t0 = (uint32_t)lat.ctrs[0];
+    const int slot = gptr(lat.r2t)[r];
+    GAS const u32x4 *src = (GAS const u32x4 *)(gptr(lat.spins) + (size_t)r * N);
+    u32x4 *lds4 = (u32x4 *)lds_raw;
+    for (uint32_t q = threadIdx.x; q < N / 16u; q += blockDim.x) lds4[q] = src[q];
+    if (KIND == 0 && threadIdx.x < 32) sthr[threadIdx.x] = gptr(lat.thr)[slot * 32 + threadIdx.x];
+    const float beta = KIND == 1 ? gptr(lat.betaf)[slot] : 0.0f;
+    const uint32_t t0 = (uint32_t)gptr(lat.ctrs)[0];
+    GAS const uint8_t *fbits = gptr(lat.fbits);
+    GAS const float *fhf = gptr(lat.fhf), *fraw = gptr(lat.fraw);
     const uint32_t nchunk = half / (4u * NW);
     __syncthreads();
     for (int sw = 0; sw < nsweep; ++sw) {
@@ -437,10 +476,9 @@ __global__ __launch_bounds__(1024) void sweep_resident(Lattice lat, int nsweep, 
             for (uint32_t ch = threadIdx.x; ch < nchunk; ch += blockDim.x) {
                 const uint32_t g0 = ch * NW, j0 = 4u * g0;
                 uint32_t W[NW], U[NW], Wnew[NW], F4[NW];
-                const uint32_t any = chunk_update<KIND, NW>(
-                    lat, sthr, own, oth, KIND == 0 ? lat.fbits + (size_t)col * half : nullptr,
-                    KIND == 1 ? lat.fhf + (size_t)col * half : nullptr, j0, g0, col, c1, r, beta, W, U,
-                    Wnew, F4);
+                const uint32_t any = chunk_update<KIND, NW>(lat, sthr, own, oth, fbits + (size_t)col * half,
+                                                            fhf + (size_t)col * half, j0, g0, col, c1, r, beta,
+                                                            W, U, Wnew, F4);
                 if (any) store_words<NW>(own, j0, Wnew);
             }
             __syncthreads();
@@ -456,18 +494,16 @@ __global__ __launch_bounds__(1024) void sweep_resident(Lattice lat, int nsweep, 
             uint32_t S1[NW], W[NW], U[NW], F1[NW];
             load_words<NW>(s1, j0, S1);
             neighbour_counts<NW>(s0, j0, c, W, U);
-            if (KIND == 0) load_words<NW>(lat.fbits + half, j0, F1);
-            chunk_energy<KIND, NW>(lat, S1, W, U, F1, KIND == 0 ? lat.fbits : nullptr,
-                                   KIND == 1 ? lat.fraw + half : nullptr, KIND == 1 ? lat.fraw : nullptr,
-                                   j0, ksum, upsum, eqsum, fsum);
+            if (KIND == 0) load_words<NW>(fbits + half, j0, F1);
+            chunk_energy<KIND, NW>(lat, S1, W, U, F1, fbits, fraw + half, fraw, j0, ksum, upsum, eqsum, fsum);
         }
         // every thread covered 4*NW sites per chunk it took; nsite per thread
         // differs, so fold the affine offsets into the total instead
         const int nch = (int)((nchunk > threadIdx.x) ? (nchunk - 1 - threadIdx.x) / blockDim.x + 1 : 0);
-        block_partial<KIND>(lat.part + (size_t)r * lat.nblk * 3, 4 * NW * nch, ksum, upsum, eqsum, fsum);
+        block_partial<KIND>(gptr(lat.part) + (size_t)r * lat.nblk * 3, 4 * NW * nch, ksum, upsum, eqsum, fsum);
     }
-    uint4 *dst = (uint4 *)(lat.spins + (size_t)r * N);
-    for (uint32_t q = threadIdx.x; q < N / 16u; q += blockDim.x) dst[q] = lds_raw[q];
+    GAS u32x4 *dst = (GAS u32x4 *)(gptr(lat.spins) + (size_t)r * N);
+    for (uint32_t q = threadIdx.x; q < N / 16u; q += blockDim.x) dst[q] = lds4[q];
 }
 
 // ---------------------------------------------------------------------
@@ -560,7 +596,8 @@ __global__ __launch_bounds__(256) void reduce_kernel(Lattice lat, int64_t *Bout,
 // Exchange step k (Eq. 2): pairs (p, p+1) with p = k mod 2; temperatures
 // move through t2r / r2t (Sec. 3.3).  One workgroup.
 // ---------------------------------------------------------------------
-__global__ __launch_bounds__(256) void exchange_kernel(Lattice lat, int tadv) {
+__global__ __launch_bounds__(256) void exchange_kernel(const Lattice *__restrict__ lats, int tadv) {
+    const Lattice &lat = lats[blockIdx.x];
     for (int r = threadIdx.x; r < lat.R; r += 256) {
         double B, F, M;
         replica_totals(lat, r, B, F, M);
@@ -628,6 +665,12 @@ int blocks_per_replica(int L, int mode, int nw, int wg) {
     return nb > kMaxFusedBlocks ? 64 : (int)nb;
 }
 
+int stream_blocks_per_replica(int L, int nw, int wg) {
+    const long long chunks = (long long)L * L * L / 8 / nw;
+    const long long w = chunks < wg ? chunks : wg;
+    return (int)(chunks / w);
+}
+
 bool fused_energy(const Lattice &lat) {
     if (lat.log2L < 3) return false;
     if (lat.mode == 1) return true;
@@ -643,56 +686,73 @@ hipError_t launch_init(const Lattice &lat, int r0, int r1, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int KIND, int ENERGY>
-static void launch_pow2(const Lattice &lat, int colour, int toff, hipStream_t s) {
-    const long long chunks = (long long)lat.N / 8 / lat.nw;
-    const int wg = chunks < lat.wg ? (int)chunks : lat.wg;
+template <int KIND, int ENERGY, bool BATCH>
+static void launch_pow2(const Launch &ln, const Lattice &lat0, int colour, int toff, hipStream_t s) {
+    const int remap = (ln.nblocks % 8 == 0) ? 1 : 0;
+    // a replica smaller than one workgroup gets a workgroup of its size:
+    // the block map counts one block per replica then, and every thread of
+    // a block must own a chunk of that replica
+    const long long chunks = (long long)ln.L * ln.L * ln.L / 8 / ln.nw;
+    const int wg = chunks < ln.wg ? (int)chunks : ln.wg;
     const int wpr = (int)(chunks / wg);
-    const int nb = wpr * lat.R;
-    const int remap = (nb % 8 == 0) ? 1 : 0;
-    if (lat.nw == 4)
-        hipLaunchKernelGGL((sweep_pow2<KIND, 4, ENERGY>), dim3(nb), dim3(wg), 0, s, lat, colour, toff, wpr, remap);
-    else if (lat.nw == 2)
-        hipLaunchKernelGGL((sweep_pow2<KIND, 2, ENERGY>), dim3(nb), dim3(wg), 0, s, lat, colour, toff, wpr, remap);
+    const dim3 grid(ln.nblocks), block(wg);
+    if (ln.nw == 4)
+        hipLaunchKernelGGL((sweep_pow2<KIND, 4, ENERGY, BATCH>), grid, block, 0, s, lat0, ln.lats, ln.map, colour,
+                           toff, remap, wpr);
+    else if (ln.nw == 2)
+        hipLaunchKernelGGL((sweep_pow2<KIND, 2, ENERGY, BATCH>), grid, block, 0, s, lat0, ln.lats, ln.map, colour,
+                           toff, remap, wpr);
     else
-        hipLaunchKernelGGL((sweep_pow2<KIND, 1, ENERGY>), dim3(nb), dim3(wg), 0, s, lat, colour, toff, wpr, remap);
+        hipLaunchKernelGGL((sweep_pow2<KIND, 1, ENERGY, BATCH>), grid, block, 0, s, lat0, ln.lats, ln.map, colour,
+                           toff, remap, wpr);
 }
 
-template <int KIND>
-static void launch_res(const Lattice &lat, int nsweep, int energy, hipStream_t s) {
-    const size_t lds = (size_t)lat.N;
-    if (lat.nw == 4)
-        hipLaunchKernelGGL((sweep_resident<KIND, 4>), dim3(lat.R), dim3(lat.wg), lds, s, lat, nsweep, energy);
-    else if (lat.nw == 2)
-        hipLaunchKernelGGL((sweep_resident<KIND, 2>), dim3(lat.R), dim3(lat.wg), lds, s, lat, nsweep, energy);
+template <int KIND, bool BATCH>
+static void launch_res(const Launch &ln, const Lattice &lat0, int nsweep, int energy, hipStream_t s) {
+    const size_t lds = (size_t)ln.L * ln.L * ln.L;
+    const dim3 grid(ln.nblocks), block(ln.wg);
+    if (ln.nw == 4)
+        hipLaunchKernelGGL((sweep_resident<KIND, 4, BATCH>), grid, block, lds, s, lat0, ln.lats, ln.map, nsweep,
+                           energy);
+    else if (ln.nw == 2)
+        hipLaunchKernelGGL((sweep_resident<KIND, 2, BATCH>), grid, block, lds, s, lat0, ln.lats, ln.map, nsweep,
+                           energy);
     else
-        hipLaunchKernelGGL((sweep_resident<KIND, 1>), dim3(lat.R), dim3(lat.wg), lds, s, lat, nsweep, energy);
+        hipLaunchKernelGGL((sweep_resident<KIND, 1, BATCH>), grid, block, lds, s, lat0, ln.lats, ln.map, nsweep,
+                           energy);
 }
 
-hipError_t launch_sweep(const Lattice &lat, int colour, int toff, int energy, hipStream_t s) {
-    const int G = lat.half >> 2;
-    if (lat.log2L >= 3) {
-        const bool e = energy && colour == 1 && fused_energy(lat);
-        if (lat.kind == 0) {
-            if (e) launch_pow2<0, 1>(lat, colour, toff, s);
-            else launch_pow2<0, 0>(lat, colour, toff, s);
-        } else {
-            if (e) launch_pow2<1, 1>(lat, colour, toff, s);
-            else launch_pow2<1, 0>(lat, colour, toff, s);
-        }
+hipError_t launch_stream_sweep(const Launch &ln, int colour, int toff, int energy, hipStream_t s) {
+    if (ln.nblocks == 0) return hipSuccess;
+    const bool e = energy && colour == 1;
+    const bool b = ln.single == nullptr;
+    const Lattice lat0 = b ? Lattice{} : *ln.single;
+    if (ln.kind == 0) {
+        if (e) b ? launch_pow2<0, 1, true>(ln, lat0, colour, toff, s) : launch_pow2<0, 1, false>(ln, lat0, colour, toff, s);
+        else b ? launch_pow2<0, 0, true>(ln, lat0, colour, toff, s) : launch_pow2<0, 0, false>(ln, lat0, colour, toff, s);
     } else {
-        dim3 grid((G + 255) / 256, lat.R);
-        if (lat.kind == 0)
-            hipLaunchKernelGGL(sweep_generic<0>, grid, dim3(256), 0, s, lat, colour, toff);
-        else
-            hipLaunchKernelGGL(sweep_generic<1>, grid, dim3(256), 0, s, lat, colour, toff);
+        if (e) b ? launch_pow2<1, 1, true>(ln, lat0, colour, toff, s) : launch_pow2<1, 1, false>(ln, lat0, colour, toff, s);
+        else b ? launch_pow2<1, 0, true>(ln, lat0, colour, toff, s) : launch_pow2<1, 0, false>(ln, lat0, colour, toff, s);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_resident(const Lattice &lat, int nsweep, int energy, hipStream_t s) {
-    if (lat.kind == 0) launch_res<0>(lat, nsweep, energy, s);
-    else launch_res<1>(lat, nsweep, energy, s);
+hipError_t launch_resident(const Launch &ln, int nsweep, int energy, hipStream_t s) {
+    if (ln.nblocks == 0) return hipSuccess;
+    const bool b = ln.single == nullptr;
+    const Lattice lat0 = b ? Lattice{} : *ln.single;
+    if (ln.kind == 0) b ? launch_res<0, true>(ln, lat0, nsweep, energy, s) : launch_res<0, false>(ln, lat0, nsweep, energy, s);
+    else b ? launch_res<1, true>(ln, lat0, nsweep, energy, s) : launch_res<1, false>(ln, lat0, nsweep, energy, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_generic_sweep(const Lattice &lat, int colour, int toff, hipStream_t s) {
+    const int G = lat.half >> 2;
+    dim3 grid((G + 255) / 256, lat.R);
+    if (lat.kind == 0)
+        hipLaunchKernelGGL(sweep_generic<0>, grid, dim3(256), 0, s, lat, colour, toff);
+    else
+        hipLaunchKernelGGL(sweep_generic<1>, grid, dim3(256), 0, s, lat, colour, toff);
     return hipGetLastError();
 }
 
@@ -706,8 +766,9 @@ hipError_t launch_reduce(const Lattice &lat, int64_t *B, double *F, int64_t *M, 
     return hipGetLastError();
 }
 
-hipError_t launch_exchange(const Lattice &lat, int tadv, hipStream_t s) {
-    hipLaunchKernelGGL(exchange_kernel, dim3(1), dim3(256), 0, s, lat, tadv);
+hipError_t launch_exchange(const Lattice *lats, int n, int tadv, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(exchange_kernel, dim3(n), dim3(256), 0, s, lats, tadv);
     return hipGetLastError();
 }
 

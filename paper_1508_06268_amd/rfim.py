@@ -28,6 +28,8 @@ EXPORTS = [
     "rfim_get_perm", "rfim_set_perm", "rfim_get_counters", "rfim_set_counters",
     "rfim_exchange_stats", "rfim_reset_exchange_stats", "rfim_save", "rfim_load",
     "rfim_set_launch_shape", "rfim_get_launch_shape",
+    "rfim_batch_create", "rfim_batch_destroy", "rfim_batch_size", "rfim_batch_sweep",
+    "rfim_batch_synchronize", "rfim_batch_item", "rfim_batch_set_shape",
 ]
 
 
@@ -88,6 +90,13 @@ def load_library(path: str = LIB_PATH):
         "rfim_load": (vp, [vp, sz, vp]),
         "rfim_set_launch_shape": (i32, [vp, i32, i32, i32]),
         "rfim_get_launch_shape": (i32, [vp, vp, vp, vp]),
+        "rfim_batch_create": (vp, [i32, vp, vp]),
+        "rfim_batch_destroy": (None, [vp]),
+        "rfim_batch_size": (i32, [vp]),
+        "rfim_batch_sweep": (i32, [vp, i64, i32]),
+        "rfim_batch_synchronize": (i32, [vp]),
+        "rfim_batch_item": (vp, [vp, i32]),
+        "rfim_batch_set_shape": (i32, [vp, i32, i32, i32, i32, i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -302,3 +311,74 @@ class Rfim:
         obj = cls._wrap(h, L)
         obj._torch_stream = stream
         return obj
+
+
+class _Borrowed(Rfim):
+    """A batch item's handle: usable for observables and state, owned by the
+    batch (closing it does nothing)."""
+
+    def close(self):
+        self._h = None
+
+
+class Batch:
+    """Many independent realizations advanced together (rfim_batch_*)."""
+
+    def __init__(self, realizations, stream=None):
+        """realizations: iterable of objects with L, R, J, h, fields, temps,
+        seed, realization and optionally R_cap / field_kind attributes."""
+        items = list(realizations)
+        n = len(items)
+        arr = (rfim_params_t * n)()
+        self._keep = []
+        self.L = []
+        for q, w in enumerate(items):
+            f = np.ascontiguousarray(w.fields, dtype=np.float32).reshape(-1)
+            T = np.ascontiguousarray(w.temps, dtype=np.float64).reshape(-1)
+            self._keep += [f, T]
+            arr[q] = rfim_params_t(int(w.L), int(w.R), int(getattr(w, "R_cap", 0) or 0), float(w.J),
+                                   float(w.h), f.ctypes.data, T.ctypes.data,
+                                   int(getattr(w, "seed", 0)) & 0xFFFFFFFFFFFFFFFF,
+                                   int(getattr(w, "realization", 0)),
+                                   int(getattr(w, "field_kind", FIELDS_AUTO)))
+            self.L.append(int(w.L))
+        self._torch_stream = stream
+        sptr = C.c_void_p(int(stream.cuda_stream)) if stream is not None else None
+        self._b = load_library().rfim_batch_create(n, arr, sptr)
+        self._keep = None
+        if not self._b:
+            raise ValueError(last_error())
+        self._items = [None] * n
+
+    def close(self):
+        if getattr(self, "_b", None):
+            self._items = []
+            load_library().rfim_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __len__(self):
+        return load_library().rfim_batch_size(self._b)
+
+    def sweep(self, n, every=0):
+        _check(load_library().rfim_batch_sweep(self._b, int(n), int(every)))
+
+    def synchronize(self):
+        _check(load_library().rfim_batch_synchronize(self._b))
+
+    def set_shape(self, L, field_kind, mode, nw, wg):
+        _check(load_library().rfim_batch_set_shape(self._b, int(L), int(field_kind), int(mode),
+                                                    int(nw), int(wg)))
+
+    def item(self, i) -> Rfim:
+        if self._items[i] is None:
+            h = load_library().rfim_batch_item(self._b, int(i))
+            if not h:
+                raise IndexError(last_error())
+            self._items[i] = _Borrowed._wrap(h, self.L[i])
+        return self._items[i]

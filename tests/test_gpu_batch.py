@@ -1,0 +1,91 @@
+"""Batched realizations: one launch per (L, field kind) class and a captured
+HIP graph per exchange interval.  Each item must reproduce the same
+realization run alone, bit for bit (both field kinds), and the +-1 items
+must match the oracle."""
+import numpy as np
+import pytest
+
+from paper_1508_06268_amd import workloads as W
+from parity_util import assert_same_state
+
+pytestmark = pytest.mark.gpu
+
+
+def _mix():
+    out = []
+    specs = [(8, 16, "b"), (16, 8, "g"), (32, 6, "b"), (8, 5, "g"), (16, 12, "b"), (64, 3, "b"),
+             (32, 4, "g"), (8, 16, "b")]
+    for rho, (L, R, kind) in enumerate(specs):
+        f = W.bimodal_fields(L, [30, rho]) if kind == "b" else W.gaussian_fields(L, [30, rho])
+        out.append(W.Realization(L=L, R=R, J=1.0, h=1.0 + 0.2 * rho, fields=f,
+                                 temps=W.geometric_temps(R, 1.0, 6.0), seed=11, realization=rho,
+                                 sweeps=0, every=10))
+    return out
+
+
+def _alone(rfim_mod, w, n, every):
+    g = rfim_mod.Rfim(w.L, w.R, w.J, w.h, w.fields, w.temps, seed=w.seed, realization=w.realization)
+    g.sweep(n, every)
+    return g
+
+
+def test_batch_items_equal_single_runs(rfim_mod):
+    mix = _mix()
+    b = rfim_mod.Batch(mix)
+    assert len(b) == len(mix)
+    for n, every in ((35, 10), (7, 10), (18, 10)):   # graph replays and ragged segments
+        b.sweep(n, every)
+    b.synchronize()
+    for q, w in enumerate(mix):
+        g = _alone(rfim_mod, w, 60, 10)
+        it = b.item(q)
+        assert np.array_equal(it.spins(), g.spins()), q
+        assert np.array_equal(it.perm(), g.perm()), q
+        assert it.counters() == g.counters() == (60, 6)
+        assert np.array_equal(it.energies(), g.energies()), q
+        ga, gc = g.exchange_stats()
+        ia, ic = it.exchange_stats()
+        assert np.array_equal(ga, ia) and np.array_equal(gc, ic)
+        g.close()
+    b.close()
+
+
+def test_batch_bimodal_items_match_oracle(rfim_mod, oracle_mod):
+    mix = [w for w in _mix() if w.fields.min() == -1.0 and np.all(np.abs(w.fields) == 1.0)]
+    b = rfim_mod.Batch(mix)
+    b.sweep(40, 10)
+    b.synchronize()
+    for q, w in enumerate(mix):
+        o = oracle_mod.Oracle(w.L, w.R, w.J, w.h, w.fields, w.temps, seed=w.seed, realization=w.realization)
+        o.sweep(40, 10)
+        assert_same_state(b.item(q), o, "batch item %d (L=%d)" % (q, w.L))
+    b.close()
+
+
+def test_batch_shapes_do_not_change_results(rfim_mod):
+    mix = _mix()
+    ref = rfim_mod.Batch(mix)
+    ref.sweep(30, 10)
+    ref.synchronize()
+    alt = rfim_mod.Batch(mix)
+    alt.set_shape(8, 0, 0, 1, 64)
+    alt.set_shape(16, 1, 0, 2, 128)
+    alt.set_shape(32, 0, 1, 4, 1024)
+    alt.set_shape(32, 1, 0, 4, 256)
+    alt.set_shape(64, 0, 0, 2, 256)
+    alt.sweep(30, 10)
+    alt.synchronize()
+    for q in range(len(mix)):
+        assert np.array_equal(ref.item(q).spins(), alt.item(q).spins()), q
+        assert np.array_equal(ref.item(q).perm(), alt.item(q).perm()), q
+    ref.close()
+    alt.close()
+
+
+def test_batch_items_refuse_standalone_sweeps(rfim_mod):
+    b = rfim_mod.Batch(_mix()[:2])
+    with pytest.raises(rfim_mod.RfimError):
+        b.item(0).sweep(1, 0)
+    with pytest.raises(rfim_mod.RfimError):
+        b.item(1).adapt_temps(1, 10, 5, 0.5, 1, 20)
+    b.close()
