@@ -211,6 +211,43 @@ rfim_t *rfim_batch_item(rfim_batch_t *b, int i);
  * used by the autotuner.  No effect on results. */
 int rfim_batch_set_shape(rfim_batch_t *b, int L, int field_kind, int mode, int nw, int wg);
 
+/* ---- pools: continuous batching for serving ------------------------- */
+
+/*
+ * A pool is a batch whose membership changes while it runs.  Realizations
+ * are admitted against a device-memory budget (each reserves what its
+ * parameters need at R_cap), advance together in quanta of whole exchange
+ * intervals (each keeps its own sweep and exchange counters; an admitted
+ * realization starts at t = 0), may run one adaptive insertion step in
+ * place between quanta, and are released when done.  A realization's
+ * chain is the same as run alone with rfim_create_ex + rfim_adapt_temps +
+ * rfim_sweep on the same schedule.  Items need L a power of two >= 8.
+ */
+typedef struct rfim_pool rfim_pool_t;
+rfim_pool_t *rfim_pool_create(size_t hbm_budget_bytes, void *hip_stream);
+void rfim_pool_destroy(rfim_pool_t *p);
+/* Device bytes a realization with these parameters reserves (0 if the
+ * parameters are invalid). */
+size_t rfim_pool_bytes_needed(const rfim_params_t *params);
+/* Admit: a slot id >= 0, RFIM_EBUSY if the budget cannot hold it now (try
+ * again after a release), or another negative status. */
+int rfim_pool_admit(rfim_pool_t *p, const rfim_params_t *params);
+/* Every active slot advances `quantum` sweeps (a multiple of
+ * exchange_every; every slot must be at an exchange boundary).  Async. */
+int rfim_pool_step(rfim_pool_t *p, int quantum, int exchange_every);
+/* One adaptive insertion step (Sec. 4) for a slot from the exchange
+ * counters it accumulated since its last reset (admission or previous
+ * step); see rfim_adapt_temps.  Synchronizes; returns the new R. */
+int rfim_pool_adapt(rfim_pool_t *p, int slot, double rate_threshold, int max_insert, int R_cap);
+int rfim_pool_release(rfim_pool_t *p, int slot);
+/* Borrowed handle of a slot for observables and state (see
+ * rfim_batch_item). */
+rfim_t *rfim_pool_item(rfim_pool_t *p, int slot);
+int rfim_pool_active(const rfim_pool_t *p);
+size_t rfim_pool_reserved(const rfim_pool_t *p);
+int rfim_pool_set_shape(rfim_pool_t *p, int L, int field_kind, int mode, int nw, int wg);
+int rfim_pool_synchronize(rfim_pool_t *p);
+
 #ifdef __cplusplus
 }
 #endif

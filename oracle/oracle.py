@@ -69,6 +69,8 @@ def lib():
         L.orc_thresholds.argtypes = [vp, vp, vp]
         L.orc_adapt_temps.argtypes = [vp, i32, i64, i32, dbl, i32, i32]
         L.orc_adapt_temps.restype = i32
+        L.orc_insert_step.argtypes = [vp, dbl, i32, i32]
+        L.orc_insert_step.restype = i32
         L.orc_philox4x32_10.argtypes = [vp, vp, vp]
         L.orc_philox4x32_10.restype = None
         _lib = L
@@ -197,6 +199,9 @@ class Oracle:
         always = np.zeros(14, dtype=np.uint8)
         lib().orc_thresholds(self._h, _p(thr), _p(always))
         return thr, always.astype(bool)
+
+    def insert_step(self, rate_threshold, max_insert, R_cap):
+        return self._check(lib().orc_insert_step(self._h, float(rate_threshold), int(max_insert), int(R_cap)))
 
     def adapt_temps(self, trials, sweeps_per_trial, every, rate_threshold, max_insert_per_trial, R_cap):
         return self._check(lib().orc_adapt_temps(self._h, int(trials), int(sweeps_per_trial), int(every),

@@ -501,6 +501,67 @@ static heap_item heap_pop(heap_item *hp, int *n) {
     return top;
 }
 
+/* One insertion step from the exchange counters accumulated since the last
+ * reset (steps 2-7 below). */
+int orc_insert_step(orc_t *o, double rate_threshold, int max_insert, int R_cap) {
+    if (max_insert < 0) { set_err("bad insert arguments"); return -1; }
+    if (R_cap > o->R_cap) { set_err("R_cap beyond the capacity given at create"); return -5; }
+    /* 2-3. exchange rate of each adjacent pair into a min-heap */
+    heap_item *hp = (heap_item *)malloc(sizeof(heap_item) * (size_t)(o->R + 1));
+    int hn = 0;
+    for (int p = 0; p + 1 < o->R; ++p)
+        if (o->att[p] > 0)
+            heap_push(hp, &hn, (heap_item){(double)o->acc[p] / (double)o->att[p], p});
+    /* 4. lowest-rate intervals below the threshold, within the caps */
+    int *picked = (int *)malloc(sizeof(int) * (size_t)(o->R + 1));
+    int count = 0;
+    while (hn > 0 && count < max_insert && o->R + count < R_cap) {
+        heap_item it = heap_pop(hp, &hn);
+        if (!(it.rate < rate_threshold)) break;
+        picked[count++] = it.p;
+    }
+    free(hp);
+    /* 5-6. midpoint temperature, new replica copies the colder end */
+    int R0 = o->R;
+    double *newT = (double *)malloc(sizeof(double) * (size_t)(R0 + count));
+    int32_t *newrep = (int32_t *)malloc(sizeof(int32_t) * (size_t)(R0 + count));
+    for (int t = 0; t < R0; ++t) { newT[t] = o->T[t]; newrep[t] = o->t2r[t]; }
+    for (int q = 0; q < count; ++q) {
+        int p = picked[q];
+        int id = R0 + q;
+        newT[R0 + q] = (o->T[p] + o->T[p + 1]) / 2.0;
+        newrep[R0 + q] = id;
+        memcpy(o->s + (size_t)id * o->N, o->s + (size_t)o->t2r[p] * o->N, (size_t)o->N);
+    }
+    /* 7. re-sort the slots by temperature (insertion sort; the new
+     * temperatures lie strictly inside distinct intervals) */
+    int Rn = R0 + count;
+    for (int a = 1; a < Rn; ++a) {
+        double tv = newT[a];
+        int32_t rv = newrep[a];
+        int b = a - 1;
+        while (b >= 0 && newT[b] > tv) {
+            newT[b + 1] = newT[b];
+            newrep[b + 1] = newrep[b];
+            --b;
+        }
+        newT[b + 1] = tv;
+        newrep[b + 1] = rv;
+    }
+    o->R = Rn;
+    for (int t = 0; t < Rn; ++t) {
+        o->T[t] = newT[t];
+        o->t2r[t] = newrep[t];
+        o->r2t[newrep[t]] = t;
+    }
+    build_tables(o);
+    orc_reset_exchange_stats(o);
+    free(newT);
+    free(newrep);
+    free(picked);
+    return o->R;
+}
+
 int orc_adapt_temps(orc_t *o, int trials, int64_t sweeps_per_trial, int every,
                     double rate_threshold, int max_insert_per_trial, int R_cap) {
     if (trials < 0 || sweeps_per_trial < 0 || every <= 0 || max_insert_per_trial < 0) {
@@ -513,59 +574,8 @@ int orc_adapt_temps(orc_t *o, int trials, int64_t sweeps_per_trial, int every,
         orc_reset_exchange_stats(o);
         int rc = orc_sweep(o, sweeps_per_trial, every);
         if (rc) return rc;
-        /* 2-3. exchange rate of each adjacent pair into a min-heap */
-        heap_item *hp = (heap_item *)malloc(sizeof(heap_item) * (size_t)(o->R + 1));
-        int hn = 0;
-        for (int p = 0; p + 1 < o->R; ++p)
-            if (o->att[p] > 0)
-                heap_push(hp, &hn, (heap_item){(double)o->acc[p] / (double)o->att[p], p});
-        /* 4. lowest-rate intervals below the threshold, within the caps */
-        int *picked = (int *)malloc(sizeof(int) * (size_t)(o->R + 1));
-        int count = 0;
-        while (hn > 0 && count < max_insert_per_trial && o->R + count < R_cap) {
-            heap_item it = heap_pop(hp, &hn);
-            if (!(it.rate < rate_threshold)) break;
-            picked[count++] = it.p;
-        }
-        free(hp);
-        /* 5-6. midpoint temperature, new replica copies the colder end */
-        int R0 = o->R;
-        double *newT = (double *)malloc(sizeof(double) * (size_t)(R0 + count));
-        int32_t *newrep = (int32_t *)malloc(sizeof(int32_t) * (size_t)(R0 + count));
-        for (int t = 0; t < R0; ++t) { newT[t] = o->T[t]; newrep[t] = o->t2r[t]; }
-        for (int q = 0; q < count; ++q) {
-            int p = picked[q];
-            int id = R0 + q;
-            newT[R0 + q] = (o->T[p] + o->T[p + 1]) / 2.0;
-            newrep[R0 + q] = id;
-            memcpy(o->s + (size_t)id * o->N, o->s + (size_t)o->t2r[p] * o->N, (size_t)o->N);
-        }
-        /* 7. re-sort the slots by temperature (insertion sort; the new
-         * temperatures lie strictly inside distinct intervals) */
-        int Rn = R0 + count;
-        for (int a = 1; a < Rn; ++a) {
-            double tv = newT[a];
-            int32_t rv = newrep[a];
-            int b = a - 1;
-            while (b >= 0 && newT[b] > tv) {
-                newT[b + 1] = newT[b];
-                newrep[b + 1] = newrep[b];
-                --b;
-            }
-            newT[b + 1] = tv;
-            newrep[b + 1] = rv;
-        }
-        o->R = Rn;
-        for (int t = 0; t < Rn; ++t) {
-            o->T[t] = newT[t];
-            o->t2r[t] = newrep[t];
-            o->r2t[newrep[t]] = t;
-        }
-        build_tables(o);
-        orc_reset_exchange_stats(o);
-        free(newT);
-        free(newrep);
-        free(picked);
+        rc = orc_insert_step(o, rate_threshold, max_insert_per_trial, R_cap);
+        if (rc < 0) return rc;
     }
     return o->R;
 }

@@ -84,6 +84,7 @@ double orc_flip_delta(const orc_t *o, int r, int i);
 int orc_thresholds(const orc_t *o, uint32_t *thr, uint8_t *always);
 
 /* Adaptive temperatures.  Returns the new R or a negative error. */
+int orc_insert_step(orc_t *o, double rate_threshold, int max_insert, int R_cap);
 int orc_adapt_temps(orc_t *o, int trials, int64_t sweeps_per_trial, int every,
                     double rate_threshold, int max_insert_per_trial, int R_cap);
 

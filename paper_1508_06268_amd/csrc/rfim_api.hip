@@ -684,6 +684,64 @@ int rfim_reset_exchange_stats(rfim_t *h) {
     return reset_stats(h);
 }
 
+// One insertion step of the adaptive method (Sec. 4) from the exchange
+// counters accumulated since the last reset: rates acc/att into a min-heap,
+// the lowest-rate intervals below the threshold get a new temperature at
+// their midpoint (at most max_insert, R <= R_cap), each new replica copies
+// the colder end and takes the next replica id; slots are re-sorted and the
+// counters reset.  Synchronizes; returns the new R.
+static int insert_step(rfim *h, double rate_threshold, int max_insert, int R_cap) {
+    int rc;
+    const int R0 = h->R;
+    std::vector<uint64_t> att(R0), acc(R0);
+    HIPCHK(hipMemcpyAsync(att.data(), h->d_att, R0 * 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(acc.data(), h->d_acc, R0 * 8, hipMemcpyDeviceToHost, h->stream));
+    std::vector<int32_t> t2r;
+    if ((rc = download_perm(h, t2r))) return rc;
+    using Item = std::pair<double, int>;
+    std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
+    for (int p = 0; p + 1 < R0; ++p)
+        if (att[p] > 0) heap.push({(double)acc[p] / (double)att[p], p});
+    std::vector<int> picked;
+    while (!heap.empty() && (int)picked.size() < max_insert && R0 + (int)picked.size() < R_cap) {
+        Item it = heap.top();
+        heap.pop();
+        if (!(it.first < rate_threshold)) break;
+        picked.push_back(it.second);
+    }
+    if (picked.empty()) {
+        if ((rc = reset_stats(h))) return rc;
+        HIPCHK(hipStreamSynchronize(h->stream));
+        return h->R;
+    }
+    std::vector<std::pair<double, int32_t>> slots;
+    for (int t = 0; t < R0; ++t) slots.push_back({h->T[t], t2r[t]});
+    for (size_t q = 0; q < picked.size(); ++q) {
+        const int p = picked[q];
+        const int32_t id = R0 + (int32_t)q;
+        slots.push_back({(h->T[p] + h->T[p + 1]) / 2.0, id});
+        HIPCHK(hipMemcpyAsync(h->d_spins + (size_t)id * h->N, h->d_spins + (size_t)t2r[p] * h->N,
+                              (size_t)h->N, hipMemcpyDeviceToDevice, h->stream));
+    }
+    std::sort(slots.begin(), slots.end(),
+              [](const std::pair<double, int32_t> &a, const std::pair<double, int32_t> &b) {
+                  return a.first < b.first;
+              });
+    h->R = (int)slots.size();
+    h->T.resize(h->R);
+    std::vector<int32_t> nt2r(h->R);
+    for (int t = 0; t < h->R; ++t) {
+        h->T[t] = slots[t].first;
+        nt2r[t] = slots[t].second;
+    }
+    if ((rc = upload_perm(h, nt2r))) return rc;
+    if ((rc = upload_tables(h))) return rc;
+    if ((rc = sync_descriptor(h))) return rc;
+    if ((rc = reset_stats(h))) return rc;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return h->R;
+}
+
 int rfim_adapt_temps(rfim_t *h, int trials, int64_t sweeps_per_trial, int exchange_every,
                      double rate_threshold, int max_insert_per_trial, int R_cap) {
     if (!h) return fail(RFIM_EINVAL, "handle is NULL");
@@ -696,58 +754,10 @@ int rfim_adapt_temps(rfim_t *h, int trials, int64_t sweeps_per_trial, int exchan
         return fail(RFIM_ECAP, "global sweep counter would pass 2^31-1");
     int rc;
     for (int trial = 0; trial < trials; ++trial) {
-        // 1. trial run, continuing the chain, with fresh exchange counters
+        // trial run, continuing the chain, with fresh exchange counters
         if ((rc = reset_stats(h))) return rc;
         if ((rc = sweep_impl(h, sweeps_per_trial, exchange_every))) return rc;
-        const int R0 = h->R;
-        std::vector<uint64_t> att(R0), acc(R0);
-        HIPCHK(hipMemcpyAsync(att.data(), h->d_att, R0 * 8, hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipMemcpyAsync(acc.data(), h->d_acc, R0 * 8, hipMemcpyDeviceToHost, h->stream));
-        std::vector<int32_t> t2r;
-        if ((rc = download_perm(h, t2r))) return rc;
-        // 2-4. rates into a min-heap; pop the lowest below the threshold
-        using Item = std::pair<double, int>;
-        std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
-        for (int p = 0; p + 1 < R0; ++p)
-            if (att[p] > 0) heap.push({(double)acc[p] / (double)att[p], p});
-        std::vector<int> picked;
-        while (!heap.empty() && (int)picked.size() < max_insert_per_trial &&
-               R0 + (int)picked.size() < R_cap) {
-            Item it = heap.top();
-            heap.pop();
-            if (!(it.first < rate_threshold)) break;
-            picked.push_back(it.second);
-        }
-        if (picked.empty()) {
-            if ((rc = reset_stats(h))) return rc;
-            continue;
-        }
-        // 5-6. midpoint temperatures; new replica ids copy the colder end
-        std::vector<std::pair<double, int32_t>> slots;
-        for (int t = 0; t < R0; ++t) slots.push_back({h->T[t], t2r[t]});
-        for (size_t q = 0; q < picked.size(); ++q) {
-            const int p = picked[q];
-            const int32_t id = R0 + (int32_t)q;
-            slots.push_back({(h->T[p] + h->T[p + 1]) / 2.0, id});
-            HIPCHK(hipMemcpyAsync(h->d_spins + (size_t)id * h->N, h->d_spins + (size_t)t2r[p] * h->N,
-                                  (size_t)h->N, hipMemcpyDeviceToDevice, h->stream));
-        }
-        // 7. re-sort slots by temperature, rebuild permutation and tables
-        std::sort(slots.begin(), slots.end(),
-                  [](const std::pair<double, int32_t> &a, const std::pair<double, int32_t> &b) {
-                      return a.first < b.first;
-                  });
-        h->R = (int)slots.size();
-        h->T.resize(h->R);
-        std::vector<int32_t> nt2r(h->R);
-        for (int t = 0; t < h->R; ++t) {
-            h->T[t] = slots[t].first;
-            nt2r[t] = slots[t].second;
-        }
-        if ((rc = upload_perm(h, nt2r))) return rc;
-        if ((rc = upload_tables(h))) return rc;
-        if ((rc = sync_descriptor(h))) return rc;
-        if ((rc = reset_stats(h))) return rc;
+        if ((rc = insert_step(h, rate_threshold, max_insert_per_trial, R_cap)) < 0) return rc;
     }
     HIPCHK(hipStreamSynchronize(h->stream));
     return h->R;
@@ -914,6 +924,7 @@ struct rfim_batch {
         int L = 0, kind = 0, mode = 0, nw = 0, wg = 0;
         std::vector<int> members;
         uint2 *d_map = nullptr;
+        size_t cap = 0;                 // entries d_map can hold
         int nblocks = 0;
     };
     std::vector<Class> classes;
@@ -962,14 +973,18 @@ int batch_build(rfim_batch *b) {
                     for (int g = 0; g < wpr; ++g) map.push_back(make_uint2(hi | (uint32_t)r, (uint32_t)g));
             }
         }
-        if (c.d_map) HIPCHK(hipFree(c.d_map));
-        c.d_map = nullptr;
         c.nblocks = (int)map.size();
-        if (!map.empty()) {
-            hipError_t e = hipMalloc((void **)&c.d_map, map.size() * sizeof(uint2));
+        if (map.size() > c.cap) {
+            if (c.d_map) HIPCHK(hipFree(c.d_map));
+            c.d_map = nullptr;
+            c.cap = 0;
+            const size_t cap = map.size() + map.size() / 2;
+            hipError_t e = hipMalloc((void **)&c.d_map, cap * sizeof(uint2));
             if (e != hipSuccess) return fail(RFIM_ENOMEM, "hipMalloc(batch map): %s", hipGetErrorString(e));
-            HIPCHK(hipMemcpyAsync(c.d_map, map.data(), map.size() * sizeof(uint2), hipMemcpyHostToDevice, b->stream));
+            c.cap = cap;
         }
+        if (!map.empty())
+            HIPCHK(hipMemcpyAsync(c.d_map, map.data(), map.size() * sizeof(uint2), hipMemcpyHostToDevice, b->stream));
     }
     HIPCHK(hipStreamSynchronize(b->stream));
     if (b->graph) {
@@ -1195,6 +1210,294 @@ int rfim_batch_sweep(rfim_batch_t *b, int64_t n, int exchange_every) {
 int rfim_batch_synchronize(rfim_batch_t *b) {
     if (!b) return fail(RFIM_EINVAL, "batch is NULL");
     HIPCHK(hipStreamSynchronize(b->stream));
+    return RFIM_OK;
+}
+
+}  // extern "C"
+
+// ===================================================================
+// Pools: a batch whose membership changes while it runs (continuous
+// batching).  Realizations are admitted against a device-memory budget,
+// advance together in quanta of whole exchange intervals (each with its own
+// sweep and exchange counters), can run an adaptive insertion step in place
+// between quanta, and are released when done.
+// ===================================================================
+struct rfim_pool {
+    rfim_batch core;                    // active items (compacted), classes, descriptors
+    std::vector<rfim *> slots;          // slot id -> item (nullptr when free)
+    std::vector<size_t> slot_bytes;
+    size_t budget = 0, reserved = 0;
+    size_t lats_cap = 0;
+    bool dirty = true;
+    struct Shape { int L, kind, mode, nw, wg; };
+    std::vector<Shape> shapes;          // per (L, kind) once seen or set
+};
+
+namespace {
+
+// Device bytes one realization reserves (what alloc_device allocates).
+size_t device_bytes(int L, int R_cap, int kind) {
+    const size_t N = (size_t)L * L * L, Rc = (size_t)R_cap;
+    size_t maxblk = 64, maxw = 1;
+    const bool pow2 = L >= 8 && (L & (L - 1)) == 0;
+    if (pow2)
+        for (int nw : {1, 2, 4})
+            for (int wg : {64, 128, 256})
+                if (rfim_dev::shape_valid(L, 0, nw, wg)) {
+                    maxblk = std::max(maxblk, (size_t)rfim_dev::blocks_per_replica(L, 0, nw, wg));
+                    maxw = std::max(maxw, (size_t)rfim_dev::stream_blocks_per_replica(L, nw, wg));
+                }
+    size_t b = Rc * N + (kind == 0 ? N : 8 * N);
+    b += Rc * (32 * 4 + 4 + 8 + 4 + 4 + 8 + 8 + 8 + 8 + 8 + 8);   // tables, perms, stats, E/B/M/F
+    b += 16 + sizeof(Lattice) + Rc * maxblk * 24 + Rc * sizeof(uint2) + (pow2 ? Rc * maxw * sizeof(uint2) : 0);
+    return b;
+}
+
+rfim_pool::Shape &pool_shape(rfim_pool *p, int L, int kind) {
+    for (auto &s : p->shapes)
+        if (s.L == L && s.kind == kind) return s;
+    rfim_pool::Shape s{L, kind, 0, 0, 0};
+    default_shape(L, 0, &s.mode, &s.nw, &s.wg);
+    p->shapes.push_back(s);
+    return p->shapes.back();
+}
+
+int pool_apply_shape(rfim_pool *p, rfim *h) {
+    const rfim_pool::Shape &s = pool_shape(p, h->L, h->kind);
+    if (h->mode == s.mode && h->nw == s.nw && h->wg == s.wg) return RFIM_OK;
+    h->mode = s.mode;
+    h->nw = s.nw;
+    h->wg = s.wg;
+    h->nblk = rfim_dev::blocks_per_replica(h->L, s.mode, s.nw, s.wg);
+    return sync_descriptor(h);
+}
+
+// Compact the active items, regroup them into classes and rebuild the
+// descriptor table and the workgroup maps.
+int pool_build(rfim_pool *p) {
+    rfim_batch &b = p->core;
+    b.items.clear();
+    for (rfim *h : p->slots)
+        if (h) b.items.push_back(h);
+    std::vector<rfim_batch::Class> old;
+    old.swap(b.classes);
+    for (int i = 0; i < (int)b.items.size(); ++i) {
+        rfim *h = b.items[i];
+        int rc = pool_apply_shape(p, h);
+        if (rc) return rc;
+        int ci = -1;
+        for (size_t c = 0; c < b.classes.size(); ++c)
+            if (b.classes[c].L == h->L && b.classes[c].kind == h->kind) ci = (int)c;
+        if (ci < 0) {
+            rfim_batch::Class c;
+            c.L = h->L;
+            c.kind = h->kind;
+            c.mode = h->mode;
+            c.nw = h->nw;
+            c.wg = h->wg;
+            for (auto &o : old)           // reuse the class's map buffer
+                if (o.L == c.L && o.kind == c.kind && o.d_map) {
+                    c.d_map = o.d_map;
+                    c.cap = o.cap;
+                    o.d_map = nullptr;
+                }
+            b.classes.push_back(c);
+            ci = (int)b.classes.size() - 1;
+        }
+        b.classes[ci].members.push_back(i);
+    }
+    for (auto &o : old)                   // classes with no members left
+        if (o.d_map) b.classes.push_back(o), b.classes.back().members.clear(), b.classes.back().nblocks = 0;
+    if (b.items.size() > p->lats_cap) {
+        if (b.d_lats) HIPCHK(hipFree(b.d_lats));
+        b.d_lats = nullptr;
+        p->lats_cap = std::max<size_t>(64, 2 * b.items.size());
+        hipError_t e = hipMalloc((void **)&b.d_lats, p->lats_cap * sizeof(Lattice));
+        if (e != hipSuccess) {
+            p->lats_cap = 0;
+            return fail(RFIM_ENOMEM, "hipMalloc(pool descriptors): %s", hipGetErrorString(e));
+        }
+    }
+    if (!b.items.empty()) {
+        int rc = batch_build(&b);
+        if (rc) return rc;
+    }
+    p->dirty = false;
+    return RFIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t rfim_pool_bytes_needed(const rfim_params_t *params) {
+    int kind = 0;
+    if (validate(params, &kind)) return 0;
+    return device_bytes(params->L, params->R_cap == 0 ? params->R : params->R_cap, kind);
+}
+
+rfim_pool_t *rfim_pool_create(size_t hbm_budget_bytes, void *hip_stream) {
+    rfim_pool *p = new (std::nothrow) rfim_pool();
+    if (!p) {
+        fail(RFIM_ENOMEM, "out of host memory");
+        return nullptr;
+    }
+    p->budget = hbm_budget_bytes;
+    if (hip_stream) {
+        p->core.stream = (hipStream_t)hip_stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&p->core.stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            fail(RFIM_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+            delete p;
+            return nullptr;
+        }
+        p->core.own_stream = true;
+    }
+    return p;
+}
+
+void rfim_pool_destroy(rfim_pool_t *p) {
+    if (!p) return;
+    // hand every live item, the class maps, the descriptors and the stream
+    // to a batch record and free that
+    rfim_batch *b = new (std::nothrow) rfim_batch();
+    if (b) {
+        b->stream = p->core.stream;
+        b->own_stream = p->core.own_stream;
+        b->d_lats = p->core.d_lats;
+        b->classes = p->core.classes;
+        for (rfim *h : p->slots)
+            if (h) b->items.push_back(h);
+        batch_free(b);
+    }
+    delete p;
+}
+
+int rfim_pool_admit(rfim_pool_t *p, const rfim_params_t *params) {
+    if (!p) return fail(RFIM_EINVAL, "pool is NULL");
+    int kind = 0;
+    int rc = validate(params, &kind);
+    if (rc) return rc;
+    if (!(params->L >= 8 && (params->L & (params->L - 1)) == 0))
+        return fail(RFIM_EINVAL, "pools need L a power of two >= 8 (got %d)", params->L);
+    const int R_cap = params->R_cap == 0 ? params->R : params->R_cap;
+    const size_t need = device_bytes(params->L, R_cap, kind);
+    if (p->reserved + need > p->budget)
+        return fail(RFIM_EBUSY, "budget: %zu reserved + %zu needed > %zu", p->reserved, need, p->budget);
+    int err = 0;
+    rfim *h = create_impl(params, p->core.stream, &err);
+    if (!h) return err ? err : RFIM_EINVAL;
+    h->in_batch = true;
+    if ((rc = init_device(h)) || (rc = pool_apply_shape(p, h))) {
+        std::string msg = g_error;
+        h->stream = nullptr;
+        free_device(h);
+        delete h;
+        g_error = msg;
+        return rc;
+    }
+    int slot = -1;
+    for (size_t s = 0; s < p->slots.size(); ++s)
+        if (!p->slots[s]) {
+            slot = (int)s;
+            break;
+        }
+    if (slot < 0) {
+        slot = (int)p->slots.size();
+        p->slots.push_back(nullptr);
+        p->slot_bytes.push_back(0);
+    }
+    p->slots[slot] = h;
+    p->slot_bytes[slot] = need;
+    p->reserved += need;
+    p->dirty = true;
+    return slot;
+}
+
+int rfim_pool_release(rfim_pool_t *p, int slot) {
+    if (!p || slot < 0 || slot >= (int)p->slots.size() || !p->slots[slot])
+        return fail(RFIM_EINVAL, "no such pool slot");
+    rfim *h = p->slots[slot];
+    HIPCHK(hipStreamSynchronize(p->core.stream));
+    h->stream = nullptr;
+    free_device(h);
+    delete h;
+    p->slots[slot] = nullptr;
+    p->reserved -= p->slot_bytes[slot];
+    p->slot_bytes[slot] = 0;
+    p->dirty = true;
+    return RFIM_OK;
+}
+
+rfim_t *rfim_pool_item(rfim_pool_t *p, int slot) {
+    if (!p || slot < 0 || slot >= (int)p->slots.size() || !p->slots[slot]) {
+        fail(RFIM_EINVAL, "no such pool slot");
+        return nullptr;
+    }
+    return p->slots[slot];
+}
+
+int rfim_pool_active(const rfim_pool_t *p) {
+    if (!p) return fail(RFIM_EINVAL, "pool is NULL");
+    int n = 0;
+    for (rfim *h : p->slots) n += h != nullptr;
+    return n;
+}
+
+size_t rfim_pool_reserved(const rfim_pool_t *p) { return p ? p->reserved : 0; }
+
+int rfim_pool_set_shape(rfim_pool_t *p, int L, int field_kind, int mode, int nw, int wg) {
+    if (!p) return fail(RFIM_EINVAL, "pool is NULL");
+    if (!rfim_dev::shape_valid(L, mode, nw, wg))
+        return fail(RFIM_EINVAL, "launch shape (%d, %d, %d) not valid for L=%d", mode, nw, wg, L);
+    HIPCHK(hipStreamSynchronize(p->core.stream));
+    rfim_pool::Shape &s = pool_shape(p, L, field_kind);
+    s.mode = mode;
+    s.nw = nw;
+    s.wg = wg;
+    p->dirty = true;
+    return RFIM_OK;
+}
+
+int rfim_pool_step(rfim_pool_t *p, int quantum, int exchange_every) {
+    if (!p) return fail(RFIM_EINVAL, "pool is NULL");
+    if (exchange_every < 1 || quantum < 1 || quantum % exchange_every)
+        return fail(RFIM_EINVAL, "quantum must be a positive multiple of exchange_every >= 1");
+    for (rfim *h : p->slots) {
+        if (!h) continue;
+        if (h->t % (uint64_t)exchange_every)
+            return fail(RFIM_ESTATE, "a pool item is not at an exchange boundary");
+        if (h->t + (uint64_t)quantum > kMaxSweeps) return fail(RFIM_ECAP, "sweep counter would pass 2^31-1");
+    }
+    int rc;
+    if (p->dirty && (rc = pool_build(p))) return rc;
+    if (p->core.items.empty()) return RFIM_OK;
+    for (int q = 0; q < quantum / exchange_every; ++q) {
+        if ((rc = batch_segment(&p->core, exchange_every, true))) return rc;
+        for (rfim *h : p->core.items) {
+            h->t += (uint64_t)exchange_every;
+            h->k += 1;
+        }
+    }
+    return RFIM_OK;
+}
+
+int rfim_pool_adapt(rfim_pool_t *p, int slot, double rate_threshold, int max_insert, int R_cap) {
+    rfim *h = rfim_pool_item(p, slot);
+    if (!h) return RFIM_EINVAL;
+    if (max_insert < 0 || std::isnan(rate_threshold)) return fail(RFIM_EINVAL, "bad adapt arguments");
+    if (R_cap > h->R_cap) return fail(RFIM_ECAP, "R_cap %d beyond the capacity %d given at admit", R_cap, h->R_cap);
+    const int R0 = h->R;
+    const int rc = insert_step(h, rate_threshold, max_insert, R_cap);
+    if (rc < 0) return rc;
+    if (rc != R0) p->dirty = true;
+    return rc;
+}
+
+int rfim_pool_synchronize(rfim_pool_t *p) {
+    if (!p) return fail(RFIM_EINVAL, "pool is NULL");
+    HIPCHK(hipStreamSynchronize(p->core.stream));
     return RFIM_OK;
 }
 

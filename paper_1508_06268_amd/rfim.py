@@ -30,6 +30,9 @@ EXPORTS = [
     "rfim_set_launch_shape", "rfim_get_launch_shape",
     "rfim_batch_create", "rfim_batch_destroy", "rfim_batch_size", "rfim_batch_sweep",
     "rfim_batch_synchronize", "rfim_batch_item", "rfim_batch_set_shape",
+    "rfim_pool_create", "rfim_pool_destroy", "rfim_pool_bytes_needed", "rfim_pool_admit",
+    "rfim_pool_step", "rfim_pool_adapt", "rfim_pool_release", "rfim_pool_item",
+    "rfim_pool_active", "rfim_pool_reserved", "rfim_pool_set_shape", "rfim_pool_synchronize",
 ]
 
 
@@ -97,6 +100,18 @@ def load_library(path: str = LIB_PATH):
         "rfim_batch_synchronize": (i32, [vp]),
         "rfim_batch_item": (vp, [vp, i32]),
         "rfim_batch_set_shape": (i32, [vp, i32, i32, i32, i32, i32]),
+        "rfim_pool_create": (vp, [sz, vp]),
+        "rfim_pool_destroy": (None, [vp]),
+        "rfim_pool_bytes_needed": (sz, [C.POINTER(rfim_params_t)]),
+        "rfim_pool_admit": (i32, [vp, C.POINTER(rfim_params_t)]),
+        "rfim_pool_step": (i32, [vp, i32, i32]),
+        "rfim_pool_adapt": (i32, [vp, i32, dbl, i32, i32]),
+        "rfim_pool_release": (i32, [vp, i32]),
+        "rfim_pool_item": (vp, [vp, i32]),
+        "rfim_pool_active": (i32, [vp]),
+        "rfim_pool_reserved": (sz, [vp]),
+        "rfim_pool_set_shape": (i32, [vp, i32, i32, i32, i32, i32]),
+        "rfim_pool_synchronize": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -382,3 +397,84 @@ class Batch:
                 raise IndexError(last_error())
             self._items[i] = _Borrowed._wrap(h, self.L[i])
         return self._items[i]
+
+
+def _params_of(w):
+    """rfim_params_t for a realization spec, plus the arrays it points to."""
+    f = np.ascontiguousarray(w.fields, dtype=np.float32).reshape(-1)
+    T = np.ascontiguousarray(w.temps, dtype=np.float64).reshape(-1)
+    prm = rfim_params_t(int(w.L), int(w.R), int(getattr(w, "R_cap", 0) or 0), float(w.J), float(w.h),
+                        f.ctypes.data, T.ctypes.data, int(getattr(w, "seed", 0)) & 0xFFFFFFFFFFFFFFFF,
+                        int(getattr(w, "realization", 0)), int(getattr(w, "field_kind", FIELDS_AUTO)))
+    return prm, (f, T)
+
+
+class Pool:
+    """Continuous batching (rfim_pool_*): realizations admitted against a
+    device-memory budget, advanced together, released when done."""
+
+    def __init__(self, budget_bytes, stream=None):
+        self._torch_stream = stream
+        sptr = C.c_void_p(int(stream.cuda_stream)) if stream is not None else None
+        self._p = load_library().rfim_pool_create(int(budget_bytes), sptr)
+        if not self._p:
+            raise ValueError(last_error())
+        self._L = {}
+
+    def close(self):
+        if getattr(self, "_p", None):
+            load_library().rfim_pool_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def bytes_needed(w) -> int:
+        prm, keep = _params_of(w)
+        return int(load_library().rfim_pool_bytes_needed(C.byref(prm)))
+
+    def admit(self, w):
+        """Slot id, or None when the budget cannot hold it now."""
+        prm, keep = _params_of(w)
+        rc = load_library().rfim_pool_admit(self._p, C.byref(prm))
+        if rc == RFIM_EBUSY:
+            return None
+        _check(rc)
+        self._L[rc] = int(w.L)
+        return rc
+
+    def step(self, quantum, every):
+        _check(load_library().rfim_pool_step(self._p, int(quantum), int(every)))
+
+    def adapt(self, slot, rate_threshold, max_insert, R_cap) -> int:
+        return _check(load_library().rfim_pool_adapt(self._p, int(slot), float(rate_threshold),
+                                                     int(max_insert), int(R_cap)))
+
+    def release(self, slot):
+        _check(load_library().rfim_pool_release(self._p, int(slot)))
+        self._L.pop(slot, None)
+
+    def item(self, slot) -> Rfim:
+        h = load_library().rfim_pool_item(self._p, int(slot))
+        if not h:
+            raise IndexError(last_error())
+        return _Borrowed._wrap(h, self._L[slot])
+
+    @property
+    def active(self) -> int:
+        return load_library().rfim_pool_active(self._p)
+
+    @property
+    def reserved(self) -> int:
+        return int(load_library().rfim_pool_reserved(self._p))
+
+    def set_shape(self, L, field_kind, mode, nw, wg):
+        _check(load_library().rfim_pool_set_shape(self._p, int(L), int(field_kind), int(mode), int(nw),
+                                                   int(wg)))
+
+    def synchronize(self):
+        _check(load_library().rfim_pool_synchronize(self._p))

@@ -1,0 +1,98 @@
+"""The GPU pool behind the serving loop: realizations admitted at different
+times into one continuously running batch, with in-place adaptive insertion.
+Each served result must equal the same realization run alone through the
+plain C ABI (rfim_create_ex + rfim_adapt_temps + rfim_sweep), and +-1 items
+must equal the oracle."""
+import numpy as np
+import pytest
+
+from paper_1508_06268_amd import workloads as W
+from paper_1508_06268_amd.serve import PoolEngine, Request, Server
+
+pytestmark = pytest.mark.gpu
+
+
+def _req(rid, arrival, L, R, kind, trial=100, prod=200, every=10, seed=5):
+    f = W.gaussian_fields(L, [50, rid]) if kind == "g" else W.bimodal_fields(L, [50, rid])
+    R_cap = (3 * R + 1) // 2
+    spec = W.Realization(L=L, R=R, J=1.0, h=1.5 + 0.05 * rid, fields=f, temps=W.linear_temps(R, 1.0, 6.0),
+                         seed=seed, realization=rid, sweeps=prod, every=every, R_cap=R_cap,
+                         adapt=dict(trials=1, sweeps_per_trial=trial, every=every, rate_threshold=0.3,
+                                    max_insert_per_trial=R_cap - R, R_cap=R_cap))
+    return Request(rid, arrival, spec)
+
+
+MIX = [(8, 16, "g"), (16, 32, "g"), (32, 16, "b"), (8, 8, "b"), (64, 8, "g"), (16, 12, "b"), (32, 8, "g")]
+
+
+def _alone(rfim_mod, w):
+    g = rfim_mod.Rfim(w.L, w.R, w.J, w.h, w.fields, w.temps, seed=w.seed, realization=w.realization,
+                      R_cap=w.R_cap)
+    a = w.adapt
+    g.adapt_temps(a["trials"], a["sweeps_per_trial"], a["every"], a["rate_threshold"],
+                  a["max_insert_per_trial"], a["R_cap"])
+    g.sweep(w.sweeps, w.every)
+    return g
+
+
+def test_served_results_equal_alone(rfim_mod):
+    reqs = [_req(q, 0.002 * q, *spec) for q, spec in enumerate(MIX)]
+    eng = PoolEngine(8 << 30)
+    res = Server(eng, quantum=50, every=10).run(reqs)
+    eng.close()
+    st = res["stats"]
+    assert st["completed"] == len(reqs), res["outcomes"]
+    for rq in reqs:
+        out = res["outcomes"][rq.rid]
+        g = _alone(rfim_mod, rq.spec)
+        assert out.R == g.R
+        assert np.array_equal(out.temps, g.temps())
+        assert np.array_equal(out.perm, g.perm()), rq.rid
+        # same chain; FP64 energy sums of per-workgroup partials may differ
+        # in the last bits between launch shapes
+        assert np.allclose(out.energies, g.energies(), rtol=1e-12, atol=1e-9), rq.rid
+        assert np.array_equal(out.magnetizations, g.magnetizations()), rq.rid
+        g.close()
+
+
+def test_pool_bimodal_items_match_oracle(rfim_mod, oracle_mod):
+    reqs = [_req(q, 0.0, L, R, "b", trial=50, prod=50) for q, (L, R) in enumerate([(8, 8), (16, 6), (32, 4)])]
+    pool = rfim_mod.Pool(4 << 30)
+    slots = [pool.admit(r.spec) for r in reqs]
+    pool.step(50, 10)
+    for s, r in zip(slots, reqs):
+        a = r.spec.adapt
+        pool.adapt(s, a["rate_threshold"], a["max_insert_per_trial"], a["R_cap"])
+    pool.step(50, 10)
+    pool.synchronize()
+    for s, r in zip(slots, reqs):
+        w = r.spec
+        o = oracle_mod.Oracle(w.L, w.R, w.J, w.h, w.fields, w.temps, seed=w.seed, realization=w.realization,
+                              R_cap=w.R_cap)
+        o.adapt_temps(1, 50, 10, a["rate_threshold"], a["max_insert_per_trial"], a["R_cap"])
+        o.sweep(50, 10)
+        it = pool.item(s)
+        assert np.array_equal(it.spins(), o.spins()), s
+        assert np.array_equal(it.perm(), o.perm())
+        assert np.array_equal(it.energies(), o.energies())
+        assert it.counters() == o.counters()
+    pool.close()
+
+
+def test_pool_budget_admission(rfim_mod):
+    r = _req(0, 0.0, 32, 16, "g")
+    need = rfim_mod.Pool.bytes_needed(r.spec)
+    assert need > 16 * 32 ** 3
+    pool = rfim_mod.Pool(2 * need + need // 2)
+    a = pool.admit(r.spec)
+    b = pool.admit(_req(1, 0.0, 32, 16, "g").spec)
+    assert a is not None and b is not None
+    assert pool.admit(_req(2, 0.0, 32, 16, "g").spec) is None      # over budget: wait
+    assert pool.reserved == 2 * need
+    pool.step(20, 10)
+    pool.release(a)
+    c = pool.admit(_req(2, 0.0, 32, 16, "g").spec)
+    assert c is not None and pool.active == 2
+    pool.step(20, 10)
+    pool.synchronize()
+    pool.close()
