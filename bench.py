@@ -173,12 +173,72 @@ def batched_leg(torch, P, W, n=256, sweeps=5000, every=10):
                        for (L, k), s in sorted(shapes.items())}}
 
 
+def served_leg(torch, P, W, n=2000, rate=50.0, budget=200 << 30, quantum=50, single_sample=200):
+    """The served workload: a Poisson stream of realization requests through
+    the continuous-batching pool (admission against the device budget, one
+    adaptive trial in place, then the production sweeps), paced by the
+    arrival times; then the same requests all at once (capacity); then a
+    sample of them one at a time through rfim_create/adapt/sweep."""
+    from paper_1508_06268_amd.serve import PoolEngine, Request, Server
+
+    stream = torch.cuda.Stream()
+    reqs = [Request(q, t, w) for q, (t, w) in enumerate(W.served_stream(n, rate))]
+    offered = sum(w.R * w.L ** 3 * (w.sweeps + w.adapt["sweeps_per_trial"]) for _, w in
+                  [(r.arrival, r.spec) for r in reqs])
+    log("served: %d requests at %.0f/s, offered >= %.2e attempts/s" % (n, rate, offered / reqs[-1].arrival))
+    # warm up the pool and its kernels on a few requests
+    warm = Server(PoolEngine(budget, stream=stream), quantum=quantum, every=10)
+    warm.run([Request(r.rid, 0.0, r.spec) for r in reqs[:8]])
+    warm.engine.close()
+    eng = PoolEngine(budget, stream=stream)
+    res = Server(eng, quantum=quantum, every=10).run(reqs)
+    eng.close()
+    st = res["stats"]
+    log("served (paced): %d done in %.2f s, p50 %.3f s, p99 %.3f s, max active %d"
+        % (st["completed"], st["wall_s"], st["latency_p50_s"], st["latency_p99_s"], st["max_active"]))
+    eng = PoolEngine(budget, stream=stream)
+    cap = Server(eng, quantum=quantum, every=10).run([Request(r.rid, 0.0, r.spec) for r in reqs])["stats"]
+    eng.close()
+    log("served (all at once): %.1f realizations/s, %.1f attempts/ns" % (cap["realizations_per_s"],
+                                                                         cap["attempts"] / cap["wall_s"] / 1e9))
+    sample = reqs[:single_sample]
+    t0 = time.perf_counter()
+    for r in sample:
+        w = r.spec
+        a = w.adapt
+        g = P.Rfim(w.L, w.R, w.J, w.h, w.fields, w.temps, seed=w.seed, realization=w.realization,
+                   R_cap=w.R_cap, stream=stream)
+        g.adapt_temps(a["trials"], a["sweeps_per_trial"], a["every"], a["rate_threshold"],
+                      a["max_insert_per_trial"], a["R_cap"])
+        g.sweep(w.sweeps, w.every)
+        g.energies()
+        g.close()
+    t_single = time.perf_counter() - t0
+    log("one at a time (first %d requests): %.2f s -> %.1f realizations/s"
+        % (len(sample), t_single, len(sample) / t_single))
+    capacity = cap["realizations_per_s"]
+    return {"workload": "served_stream", "requests": n, "arrival_rate_per_s": rate,
+            "budget_bytes": budget, "quantum_sweeps": quantum,
+            "paced": {"realizations_per_s": round(st["realizations_per_s"], 2),
+                      "latency_p50_s": round(st["latency_p50_s"], 4),
+                      "latency_p99_s": round(st["latency_p99_s"], 4),
+                      "latency_mean_s": round(st["latency_mean_s"], 4), "wall_s": round(st["wall_s"], 2),
+                      "max_active": st["max_active"], "failed": st["failed"]},
+            "capacity_realizations_per_s": round(capacity, 2),
+            "capacity_attempts_per_ns": round(cap["attempts"] / cap["wall_s"] / 1e9, 1),
+            "utilization": round(rate / capacity, 3) if capacity else None,
+            "single_loop_realizations_per_s": round(len(sample) / t_single, 2),
+            "single_loop_sample": len(sample),
+            "capacity_vs_single_loop": round(capacity * t_single / len(sample), 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="adaptive_l64", choices=["adaptive_l64"])
+    ap.add_argument("--workload", default="adaptive_l64", choices=["adaptive_l64", "served_stream"],
+                    help="served_stream: the continuous-batching serving run (its own JSON line)")
     ap.add_argument("--production-sweeps", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="bench", choices=["bench", "kernel", "copy"],
@@ -203,6 +263,13 @@ def main():
         return
     if args.mode == "copy":
         copy_only(torch, args.copy_bytes)
+        return
+    if args.workload == "served_stream":
+        served = served_leg(torch, P, W)
+        print(json.dumps({"metric": METRIC, "value": served["paced"]["realizations_per_s"],
+                          "unit": "realizations/s", "n_gpus": 1, "higher_is_better": True,
+                          "dtype": "u8", "data": "synthetic",
+                          "config": {"workload": "served_stream"}, "served": served}), flush=True)
         return
     w = W.adaptive_l64(sweeps=args.production_sweeps)
     stream = torch.cuda.Stream()

@@ -277,7 +277,7 @@ int upload_fields(rfim *h) {
         std::vector<float> hf(N), raw(N);
         for_each_site(h->L, [&](size_t i, int c, size_t j) {
             raw[c * half + j] = h->fields[i];
-            hf[c * half + j] = (float)(h->h * (double)h->fields[i]);
+            hf[c * half + j] = (float)(h->h * (double)h->fields[i] - 6.0 * h->J);
         });
         HIPCHK(hipMemcpyAsync(h->d_fhf, hf.data(), N * 4, hipMemcpyHostToDevice, h->stream));
         HIPCHK(hipMemcpyAsync(h->d_fraw, raw.data(), N * 4, hipMemcpyHostToDevice, h->stream));

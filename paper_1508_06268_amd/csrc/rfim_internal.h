@@ -12,7 +12,7 @@ namespace rfim_dev {
 //          Colour c, sublattice index j holds site 2j or 2j+1 (whichever has
 //          colour c).
 //   fbits  uint8 [2][N/2]         +-1 fields: byte = 4 iff h_i = +1, else 0.
-//   fhf    float [2][N/2]         continuous fields: (float)(h * h_i).
+//   fhf    float [2][N/2]         continuous fields: (float)(h * h_i - 6 J).
 //   fraw   float [2][N/2]         continuous fields: h_i as given.
 //   thr    uint32 [R_cap][32]     per slot, +-1 fields: threshold indexed by
 //                                 (up << 2) | (b << 1) | f with up = number of

@@ -72,11 +72,18 @@ __device__ __forceinline__ uint32_t word_at(const Words &w, int q) {
     return q == 0 ? w.w0 : q == 1 ? w.w1 : q == 2 ? w.w2 : w.w3;
 }
 
-// exp(-beta dE) * 2^32 as an integer threshold in FP32 (continuous fields).
-__device__ __forceinline__ uint32_t cont_threshold(float beta, float dE) {
-    const float p = expf(-(beta * dE));
-    const float scaled = fminf(p * 4294967296.0f, 4294967040.0f);
-    return (uint32_t)scaled;
+// Continuous fields, one site, in FP32.  With up = number of +1 neighbours,
+// J n + h h_i = 2J up + (h h_i - 6J) = y (the second term precomputed per
+// site), and the flip costs dE = 2 s y.  With a = -2 beta log2(e),
+// exp(-beta dE) = 2^(s a y): accept iff s a y >= 0 (dE <= 0) or
+// u32 2^-32 < 2^(s a y).
+__device__ __forceinline__ bool cont_accept(float up, float hfs, float twoJ, float a, bool up_spin,
+                                            uint32_t u) {
+    const float y = fmaf(twoJ, up, hfs);
+    const float ta = a * y;
+    const float t = up_spin ? ta : -ta;
+    const float p = __builtin_amdgcn_exp2f(t);
+    return t >= 0.0f || (float)u * 0x1p-32f < p;
 }
 
 // ---------------------------------------------------------------------
@@ -139,11 +146,8 @@ __global__ __launch_bounds__(256) void sweep_generic(Lattice lat, int colour, in
             const int idx = (up << 2) | (b << 1) | f;
             accept = ((lat.always_mask >> idx) & 1u) || u < lat.thr[slot * 32 + idx];
         } else {
-            const float n = (float)(2 * up - 6);
-            const float s = b ? 1.0f : -1.0f;
-            const float xloc = lat.Jf * n + lat.fhf[(size_t)colour * lat.half + j];
-            const float dE = 2.0f * s * xloc;
-            accept = dE <= 0.0f || u < cont_threshold(lat.betaf[slot], dE);
+            const float a = -2.0f * 1.44269504088896341f * lat.betaf[slot];
+            accept = cont_accept((float)up, lat.fhf[(size_t)colour * lat.half + j], 2.0f * lat.Jf, a, b != 0, u);
         }
         if (accept) own[j] = (uint8_t)(b ^ 1);
     }
@@ -277,21 +281,16 @@ __device__ __forceinline__ uint32_t bimodal_flips(const uint32_t *sthr, uint32_t
     return fl;
 }
 
-// Continuous fields: dE = 2 s (J n + h h_i) and exp(-beta dE) in FP32.
-__device__ __forceinline__ uint32_t continuous_flips(uint32_t U, uint32_t Wown, const f32x4 hf, float Jf,
-                                                     float beta, const Words &rw) {
-    const float hv[4] = {hf.x, hf.y, hf.z, hf.w};
-    uint32_t fl = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int up = (U >> (8 * q)) & 0xFF;
-        const float n = (float)(2 * up - 6);
-        const float s = ((Wown >> (8 * q)) & 1u) ? 1.0f : -1.0f;
-        const float xloc = Jf * n + hv[q];
-        const float dE = 2.0f * s * xloc;
-        const bool acc = dE <= 0.0f || word_at(rw, q) < cont_threshold(beta, dE);
-        fl |= (acc ? 1u : 0u) << (8 * q);
-    }
+// Continuous fields: four sites of one Philox block (see cont_accept).
+__device__ __forceinline__ uint32_t continuous_flips(uint32_t U, uint32_t Wown, const f32x4 hf, float twoJ,
+                                                     float a, const Words &rw) {
+    // byte-to-float conversions (one v_cvt_f32_ubyteN each)
+    const float up0 = (float)(U & 0xFFu), up1 = (float)((U >> 8) & 0xFFu);
+    const float up2 = (float)((U >> 16) & 0xFFu), up3 = (float)(U >> 24);
+    uint32_t fl = cont_accept(up0, hf.x, twoJ, a, Wown & 0x1u, rw.w0) ? 0x1u : 0u;
+    fl |= cont_accept(up1, hf.y, twoJ, a, Wown & 0x100u, rw.w1) ? 0x100u : 0u;
+    fl |= cont_accept(up2, hf.z, twoJ, a, Wown & 0x10000u, rw.w2) ? 0x10000u : 0u;
+    fl |= cont_accept(up3, hf.w, twoJ, a, Wown & 0x1000000u, rw.w3) ? 0x1000000u : 0u;
     return fl;
 }
 
@@ -318,7 +317,7 @@ __device__ __forceinline__ uint32_t chunk_update(const Lattice &lat, const uint3
             fl = bimodal_flips(sthr, U[w], Wown[w], F4[w], rw, lat.always_mask);
         } else {
             const f32x4 hf = *(typename rebind_ptr<PF, const f32x4>::type)(hf_own + j0 + 4u * w);
-            fl = continuous_flips(U[w], Wown[w], hf, lat.Jf, beta, rw);
+            fl = continuous_flips(U[w], Wown[w], hf, 2.0f * lat.Jf, -2.0f * 1.44269504088896341f * beta, rw);
         }
         any |= fl;
         Wnew[w] = Wown[w] ^ fl;
