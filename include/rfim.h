@@ -161,6 +161,15 @@ int rfim_set_counters(rfim_t *h, uint64_t t, uint64_t k);
 int rfim_exchange_stats(rfim_t *h, uint64_t *att, uint64_t *acc);
 int rfim_reset_exchange_stats(rfim_t *h);
 
+/* Measurements (Sec. 7): after every exchange step the energy E and
+ * magnetisation M of the replica at each temperature slot are added to
+ * per-slot sums.  obs = host [R][6]: count, sum E, sum E^2, sum |M|,
+ * sum M^2, sum M^4 (FP64).  Reset at creation, by rfim_reset_observables
+ * and by every insertion of rfim_adapt_temps (the slots change).
+ * Synchronizes. */
+int rfim_observables(rfim_t *h, double *obs);
+int rfim_reset_observables(rfim_t *h);
+
 /* Launch shape of the sweep kernels (no effect on results: every shape
  * gives bit-identical chains).  For L = 2^l >= 8: mode 0 streams every
  * half-sweep through HBM with nw in {1, 2, 4} dwords (4 sites each) per

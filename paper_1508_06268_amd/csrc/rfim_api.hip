@@ -63,7 +63,7 @@ struct rfim {
     uint8_t *d_spins = nullptr, *d_fbits = nullptr;
     float *d_fhf = nullptr, *d_fraw = nullptr, *d_betaf = nullptr;
     uint32_t *d_thr = nullptr;
-    double *d_beta = nullptr, *d_part = nullptr, *d_E = nullptr;
+    double *d_beta = nullptr, *d_part = nullptr, *d_E = nullptr, *d_Mr = nullptr, *d_obs = nullptr;
     int32_t *d_t2r = nullptr, *d_r2t = nullptr;
     uint64_t *d_att = nullptr, *d_acc = nullptr, *d_ctrs = nullptr;
     int64_t *d_B = nullptr, *d_M = nullptr;
@@ -111,6 +111,8 @@ struct rfim {
         a.nw = nw;
         a.wg = wg;
         a.E = d_E;
+        a.Mr = d_Mr;
+        a.obs = d_obs;
         return a;
     }
 };
@@ -120,7 +122,8 @@ namespace {
 void free_device(rfim *h) {
     void *ptrs[] = {h->d_spins, h->d_fbits, h->d_fhf, h->d_fraw, h->d_betaf, h->d_thr,
                     h->d_beta,  h->d_part,  h->d_E,   h->d_t2r,  h->d_r2t,   h->d_att,
-                    h->d_acc,   h->d_ctrs,  h->d_B,   h->d_M,    h->d_F};
+                    h->d_acc,   h->d_ctrs,  h->d_B,   h->d_M,    h->d_F,     h->d_Mr,
+                    h->d_obs};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (h->d_lat) (void)hipFree(h->d_lat);
@@ -247,6 +250,8 @@ int alloc_device(rfim *h) {
     ALLOC(h->d_ctrs, 2 * sizeof(uint64_t));
     ALLOC(h->d_part, Rc * (size_t)maxblk * 3 * sizeof(double));
     ALLOC(h->d_E, Rc * sizeof(double));
+    ALLOC(h->d_Mr, Rc * sizeof(double));
+    ALLOC(h->d_obs, Rc * 6 * sizeof(double));
     ALLOC(h->d_B, Rc * sizeof(int64_t));
     ALLOC(h->d_M, Rc * sizeof(int64_t));
     ALLOC(h->d_F, Rc * sizeof(double));
@@ -343,6 +348,11 @@ int reset_stats(rfim *h) {
     return RFIM_OK;
 }
 
+int reset_obs(rfim *h) {
+    HIPCHK(hipMemsetAsync(h->d_obs, 0, (size_t)h->R_cap * 6 * sizeof(double), h->stream));
+    return RFIM_OK;
+}
+
 int download_perm(rfim *h, std::vector<int32_t> &t2r) {
     t2r.resize(h->R);
     HIPCHK(hipMemcpyAsync(t2r.data(), h->d_t2r, h->R * 4, hipMemcpyDeviceToHost, h->stream));
@@ -429,6 +439,7 @@ int init_device(rfim *h) {
     if ((rc = upload_perm(h, ident))) return rc;
     if ((rc = upload_counters(h))) return rc;
     if ((rc = reset_stats(h))) return rc;
+    if ((rc = reset_obs(h))) return rc;
     if ((rc = sync_descriptor(h))) return rc;
     HIPCHK(rfim_dev::launch_init(h->lattice(), 0, h->R, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
@@ -738,6 +749,7 @@ static int insert_step(rfim *h, double rate_threshold, int max_insert, int R_cap
     if ((rc = upload_tables(h))) return rc;
     if ((rc = sync_descriptor(h))) return rc;
     if ((rc = reset_stats(h))) return rc;
+    if ((rc = reset_obs(h))) return rc;      // the slots changed
     HIPCHK(hipStreamSynchronize(h->stream));
     return h->R;
 }
@@ -761,6 +773,18 @@ int rfim_adapt_temps(rfim_t *h, int trials, int64_t sweeps_per_trial, int exchan
     }
     HIPCHK(hipStreamSynchronize(h->stream));
     return h->R;
+}
+
+int rfim_observables(rfim_t *h, double *obs) {
+    if (!h || !obs) return fail(RFIM_EINVAL, "NULL argument");
+    HIPCHK(hipMemcpyAsync(obs, h->d_obs, (size_t)h->R * 6 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return RFIM_OK;
+}
+
+int rfim_reset_observables(rfim_t *h) {
+    if (!h) return fail(RFIM_EINVAL, "handle is NULL");
+    return reset_obs(h);
 }
 
 int rfim_set_launch_shape(rfim_t *h, int mode, int nw, int wg) {

@@ -25,6 +25,10 @@ namespace rfim_dev {
 //   part   double [R_cap][nblk][3] energy partials (B, F, M) per block;
 //                                 nblk = blocks_per_replica(shape).
 //   E      double [R_cap]         energy by replica id after a reduction.
+//   Mr     double [R_cap]         magnetisation by replica id (same reduction).
+//   obs    double [R_cap][6]      per slot, one sample per exchange step
+//                                 (Sec. 7): count, sum E, sum E^2, sum |M|,
+//                                 sum M^2, sum M^4.
 struct Lattice {
     int L, N, half, R;          // R = replicas currently active
     int log2L;                  // >= 3 when L is a power of two, else -1
@@ -47,6 +51,8 @@ struct Lattice {
     int mode;                   // power-of-two L: 0 streaming, 1 LDS-resident
     int nw, wg;                 // dwords per thread, threads per workgroup
     double *E;
+    double *Mr;
+    double *obs;
 };
 
 // Above this many workgroups per replica the streaming sweep does not write

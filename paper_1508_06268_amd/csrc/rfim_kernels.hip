@@ -601,6 +601,7 @@ __global__ __launch_bounds__(256) void exchange_kernel(const Lattice *__restrict
         double B, F, M;
         replica_totals(lat, r, B, F, M);
         lat.E[r] = energy_of(lat, B, F);
+        lat.Mr[r] = M;
     }
     const uint64_t k = lat.ctrs[1];
     __syncthreads();
@@ -620,6 +621,18 @@ __global__ __launch_bounds__(256) void exchange_kernel(const Lattice *__restrict
         }
     }
     __syncthreads();
+    // one measurement per exchange step (Sec. 7), by temperature slot
+    for (int t = threadIdx.x; t < lat.R; t += 256) {
+        const int a = lat.t2r[t];
+        const double e = lat.E[a], m = lat.Mr[a], m2 = m * m;
+        double *o = lat.obs + 6 * (size_t)t;
+        o[0] += 1.0;
+        o[1] += e;
+        o[2] += e * e;
+        o[3] += fabs(m);
+        o[4] += m2;
+        o[5] += m2 * m2;
+    }
     if (threadIdx.x == 0) {
         lat.ctrs[0] += (uint64_t)tadv;
         lat.ctrs[1] = k + 1;

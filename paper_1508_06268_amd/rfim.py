@@ -27,7 +27,7 @@ EXPORTS = [
     "rfim_magnetizations", "rfim_components", "rfim_get_spins", "rfim_set_spins",
     "rfim_get_perm", "rfim_set_perm", "rfim_get_counters", "rfim_set_counters",
     "rfim_exchange_stats", "rfim_reset_exchange_stats", "rfim_save", "rfim_load",
-    "rfim_set_launch_shape", "rfim_get_launch_shape",
+    "rfim_set_launch_shape", "rfim_get_launch_shape", "rfim_observables", "rfim_reset_observables",
     "rfim_batch_create", "rfim_batch_destroy", "rfim_batch_size", "rfim_batch_sweep",
     "rfim_batch_synchronize", "rfim_batch_item", "rfim_batch_set_shape",
     "rfim_pool_create", "rfim_pool_destroy", "rfim_pool_bytes_needed", "rfim_pool_admit",
@@ -93,6 +93,8 @@ def load_library(path: str = LIB_PATH):
         "rfim_load": (vp, [vp, sz, vp]),
         "rfim_set_launch_shape": (i32, [vp, i32, i32, i32]),
         "rfim_get_launch_shape": (i32, [vp, vp, vp, vp]),
+        "rfim_observables": (i32, [vp, vp]),
+        "rfim_reset_observables": (i32, [vp]),
         "rfim_batch_create": (vp, [i32, vp, vp]),
         "rfim_batch_destroy": (None, [vp]),
         "rfim_batch_size": (i32, [vp]),
@@ -299,6 +301,15 @@ class Rfim:
                     R_cap):
         return rfim_adapt_temps(self._h, trials, sweeps_per_trial, every, rate_threshold,
                                 max_insert_per_trial, R_cap)
+
+    def observables(self) -> np.ndarray:
+        """Per slot: [count, sum E, sum E^2, sum |M|, sum M^2, sum M^4]."""
+        o = np.zeros((self.R, 6), dtype=np.float64)
+        _check(load_library().rfim_observables(self._h, _p(o)))
+        return o
+
+    def reset_observables(self):
+        _check(load_library().rfim_reset_observables(self._h))
 
     def launch_shape(self):
         m, nw, wg = C.c_int(), C.c_int(), C.c_int()

@@ -1,0 +1,99 @@
+"""Full-size workloads in the launch configuration the benchmark times.
+The oracle cannot replay 10^4-sweep runs at L=64, so these check properties
+that hold at any size and sampled parity: the GPU's final state is loaded
+into the oracle and one more exchange interval is compared bit for bit."""
+import numpy as np
+import pytest
+
+from paper_1508_06268_amd import workloads as W
+from parity_util import assert_same_state
+
+pytestmark = pytest.mark.gpu
+
+
+def _properties(g, h, R_max, t, k):
+    s = g.spins()
+    assert set(np.unique(s)) <= {-1, 1}
+    p = g.perm()
+    assert sorted(p.tolist()) == list(range(g.R))
+    T = g.temps()
+    assert np.all(np.diff(T) > 0) and g.R <= R_max
+    assert g.counters() == (t, k)
+    att, acc = g.exchange_stats()
+    assert np.all(acc <= att)
+    # energies reduced inside the sweep kernel (exchange path) and by the
+    # separate recompute kernel agree exactly for +-1 fields
+    B, F, M = g.components()
+    E_slot = g.energies()
+    E_rep = -(1.0 * B.astype(np.float64)) - (h * F)
+    assert np.array_equal(E_slot, E_rep[p])
+    assert np.array_equal(g.magnetizations(), M[p])
+    assert np.array_equal(M, s.astype(np.int64).sum(axis=1))
+
+
+def test_adaptive_l64_full_run(rfim_mod, oracle_mod):
+    w = W.adaptive_l64()
+    g = rfim_mod.Rfim(w.L, w.R, w.J, w.h, w.fields, w.temps, seed=w.seed, R_cap=w.R_cap)
+    a = w.adapt
+    for _ in range(a["trials"]):
+        g.adapt_temps(1, a["sweeps_per_trial"], a["every"], a["rate_threshold"], a["max_insert_per_trial"],
+                      a["R_cap"])
+    R_after = g.R
+    assert 128 < R_after <= 192
+    g.sweep(w.sweeps, w.every)
+    n = a["trials"] * a["sweeps_per_trial"] + w.sweeps
+    _properties(g, w.h, 192, n, n // w.every)
+    # sampled parity: continue both from the GPU's final state
+    o = oracle_mod.Oracle(w.L, R_after, w.J, w.h, w.fields, g.temps(), seed=w.seed, R_cap=w.R_cap)
+    o.set_spins(g.spins())
+    o.set_perm(g.perm())
+    o.set_counters(*g.counters())
+    g.reset_exchange_stats()
+    o.reset_exchange_stats()
+    g.sweep(10, 10)
+    o.sweep(10, 10)
+    assert_same_state(g, o, "after the full L=64 adaptive run")
+    g.close()
+
+
+def test_paper_scale_l32_continuous_full_run(rfim_mod, oracle_mod):
+    w = W.paper_scale_l32()
+    g = rfim_mod.Rfim(w.L, w.R, w.J, w.h, w.fields, w.temps, seed=w.seed)
+    g.sweep(w.sweeps, w.every)
+    assert g.counters() == (w.sweeps, w.sweeps // w.every)
+    s = g.spins()
+    p = g.perm()
+    B, F, M = g.components()
+    # FP64 energies from two reduction orders agree to rounding
+    E_rep = -(w.J * B.astype(np.float64)) - (w.h * F)
+    assert np.allclose(g.energies(), E_rep[p], rtol=1e-12)
+    # sampled parity: one sweep from the final state, decision by decision
+    o = oracle_mod.Oracle(w.L, w.R, w.J, w.h, w.fields, w.temps, seed=w.seed)
+    o.set_spins(s)
+    o.set_perm(p)
+    o.set_counters(*g.counters())
+    g.sweep(1, 0)
+    o.sweep(1, 0)
+    mism = int((g.spins() != o.spins()).sum())
+    assert mism <= 2, mism                 # 2.1e6 decisions, rate << 1e-6
+    # colder slots hold lower energies on average
+    E = g.energies()
+    assert E[:8].mean() < E[-8:].mean()
+    g.close()
+
+
+def test_batched_mix_full_size_sampled(rfim_mod):
+    specs = W.batched_mix(256, 5000)
+    b = rfim_mod.Batch(specs)
+    b.sweep(5000, 10)
+    b.synchronize()
+    for q in (0, 1, 2, 3, 101, 254, 255):
+        w = specs[q]
+        g = rfim_mod.Rfim(w.L, w.R, w.J, w.h, w.fields, w.temps, seed=w.seed, realization=w.realization)
+        g.sweep(5000, 10)
+        it = b.item(q)
+        assert np.array_equal(it.spins(), g.spins()), q
+        assert np.array_equal(it.perm(), g.perm()), q
+        assert it.counters() == g.counters() == (5000, 500)
+        g.close()
+    b.close()

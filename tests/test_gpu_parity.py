@@ -168,3 +168,22 @@ def test_invalid_launch_shape_rejected(rfim_mod):
     g64 = rfim_mod.Rfim(64, 1, 1.0, 1.0, W.bimodal_fields(64, [0, 0]), [1.0])
     with pytest.raises(rfim_mod.RfimError):
         g64.set_launch_shape(1, 4, 1024)       # a 64^3 replica does not fit in LDS
+
+
+def test_observables_match_oracle_replay(rfim_mod, oracle_mod):
+    """The per-slot sums the exchange kernel keeps equal a replay that reads
+    the oracle's energies and magnetisations after every exchange step."""
+    L, R = 8, 6
+    f = W.bimodal_fields(L, [18, 0])
+    T = W.linear_temps(R, 1.5, 5.0)
+    g, o = make_pair(rfim_mod, oracle_mod, L, R, 1.0, 1.0, f, T, seed=8)
+    g.sweep(100, 10)
+    want = np.zeros((R, 6))
+    for _ in range(10):
+        o.sweep(10, 10)
+        E = o.energies()
+        M = o.magnetizations().astype(np.float64)
+        want += np.stack([np.ones(R), E, E * E, np.abs(M), M * M, M ** 4], axis=1)
+    assert np.array_equal(g.observables(), want)
+    g.reset_observables()
+    assert not g.observables().any()
