@@ -186,17 +186,25 @@ def served_leg(torch, P, W, n=2000, rate=50.0, budget=200 << 30, quantum=50, sin
     offered = sum(w.R * w.L ** 3 * (w.sweeps + w.adapt["sweeps_per_trial"]) for _, w in
                   [(r.arrival, r.spec) for r in reqs])
     log("served: %d requests at %.0f/s, offered >= %.2e attempts/s" % (n, rate, offered / reqs[-1].arrival))
+    # launch shapes per (L, field kind) from the autotuner (cached)
+    from paper_1508_06268_amd import autotune
+
+    probe = []
+    for L in (8, 16, 32, 64):
+        probe += [r.spec for r in reqs if r.spec.L == L][:8]
+    shapes = autotune.tune(probe, every=10)
+    log("served: shapes %s" % {k: v for k, v in sorted(shapes.items())})
     # warm up the pool and its kernels on a few requests
-    warm = Server(PoolEngine(budget, stream=stream), quantum=quantum, every=10)
+    warm = Server(PoolEngine(budget, stream=stream, shapes=shapes), quantum=quantum, every=10)
     warm.run([Request(r.rid, 0.0, r.spec) for r in reqs[:8]])
     warm.engine.close()
-    eng = PoolEngine(budget, stream=stream)
+    eng = PoolEngine(budget, stream=stream, shapes=shapes)
     res = Server(eng, quantum=quantum, every=10).run(reqs)
     eng.close()
     st = res["stats"]
     log("served (paced): %d done in %.2f s, p50 %.3f s, p99 %.3f s, max active %d"
         % (st["completed"], st["wall_s"], st["latency_p50_s"], st["latency_p99_s"], st["max_active"]))
-    eng = PoolEngine(budget, stream=stream)
+    eng = PoolEngine(budget, stream=stream, shapes=shapes)
     cap = Server(eng, quantum=quantum, every=10).run([Request(r.rid, 0.0, r.spec) for r in reqs])["stats"]
     eng.close()
     log("served (all at once): %.1f realizations/s, %.1f attempts/ns" % (cap["realizations_per_s"],
@@ -229,7 +237,8 @@ def served_leg(torch, P, W, n=2000, rate=50.0, budget=200 << 30, quantum=50, sin
             "utilization": round(rate / capacity, 3) if capacity else None,
             "single_loop_realizations_per_s": round(len(sample) / t_single, 2),
             "single_loop_sample": len(sample),
-            "capacity_vs_single_loop": round(capacity * t_single / len(sample), 2)}
+            "capacity_vs_single_loop": round(capacity * t_single / len(sample), 2),
+            "shapes": {"L%d_%s" % (L, "pm1" if k == 0 else "gauss"): list(v) for (L, k), v in sorted(shapes.items())}}
 
 
 def main():

@@ -89,3 +89,30 @@ def test_batch_items_refuse_standalone_sweeps(rfim_mod):
     with pytest.raises(rfim_mod.RfimError):
         b.item(1).adapt_temps(1, 10, 5, 0.5, 1, 20)
     b.close()
+
+
+def test_every_graph_replay_matches_eager(rfim_mod):
+    """The captured interval graph is replayed several times with eager work
+    and synchronizations in between; after every replay each item equals the
+    same realization advanced eagerly (no graph) one interval at a time."""
+    mix = _mix()[:4]
+    b = rfim_mod.Batch(mix)
+    singles = [rfim_mod.Rfim(w.L, w.R, w.J, w.h, w.fields, w.temps, seed=w.seed, realization=w.realization)
+               for w in mix]
+    for rep in range(4):
+        b.sweep(10, 10)                       # one graph replay
+        b.synchronize()
+        for q, g in enumerate(singles):
+            g.sweep(10, 10)                   # eager launches
+            it = b.item(q)
+            assert np.array_equal(it.spins(), g.spins()), (rep, q)
+            assert np.array_equal(it.perm(), g.perm()), (rep, q)
+            assert np.array_equal(it.energies(), g.energies()), (rep, q)
+        if rep == 1:
+            b.sweep(3, 10)                    # an eager ragged segment between replays
+            b.sweep(7, 10)
+            for g in singles:
+                g.sweep(10, 10)
+    for g in singles:
+        g.close()
+    b.close()

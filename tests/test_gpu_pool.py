@@ -69,6 +69,7 @@ def test_pool_bimodal_items_match_oracle(rfim_mod, oracle_mod):
         w = r.spec
         o = oracle_mod.Oracle(w.L, w.R, w.J, w.h, w.fields, w.temps, seed=w.seed, realization=w.realization,
                               R_cap=w.R_cap)
+        a = w.adapt
         o.adapt_temps(1, 50, 10, a["rate_threshold"], a["max_insert_per_trial"], a["R_cap"])
         o.sweep(50, 10)
         it = pool.item(s)
@@ -76,6 +77,8 @@ def test_pool_bimodal_items_match_oracle(rfim_mod, oracle_mod):
         assert np.array_equal(it.perm(), o.perm())
         assert np.array_equal(it.energies(), o.energies())
         assert it.counters() == o.counters()
+        assert it.R == o.R
+    assert sum(pool.item(s).R for s in slots) > sum(r.spec.R for r in reqs)   # insertions happened
     pool.close()
 
 
