@@ -335,7 +335,7 @@ def main():
     traffic = measured_traffic(bytes_per_launch)
     roofline = {"bound": "alu", "achieved": round(alu_tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
                 "unit": "TOP/s", "frac": round(alu_tops / VALU_PEAK_TOPS, 4), "traffic": traffic,
-                "kernel": "sweep_pow2<bimodal, 4 dwords/thread>", "launch_us": round(launch_us, 3),
+                "kernel": "sweep_pow2<bimodal, 4 dwords x 128 threads>", "launch_us": round(launch_us, 3),
                 "attempts_per_launch": attempts_per_launch,
                 "ops_per_attempt": VALU_SLOTS_PER_ATTEMPT,
                 "attempts_per_ns_kernel": round(attempts_per_launch / (launch_us * 1e3), 1),
