@@ -172,13 +172,27 @@ int rfim_reset_observables(rfim_t *h);
 
 /* Launch shape of the sweep kernels (no effect on results: every shape
  * gives bit-identical chains).  For L = 2^l >= 8: mode 0 streams every
- * half-sweep through HBM with nw in {1, 2, 4} dwords (4 sites each) per
- * thread and wg in {64, 128, 256} threads per workgroup; mode 1 (L <= 32)
+ * half-sweep through HBM with nw in {1, 2, 4, 8} dwords (4 sites each, at
+ * most one row: 4 nw <= L/2) per thread and wg in {64, 128, 256} threads
+ * per workgroup; mode 1 (L <= 32, nw <= 4)
  * keeps each replica in one workgroup's LDS (wg in {64, ..., 1024}) for all
  * sweeps of an exchange interval.  Other L have the single shape (0, 0, 0).
  * RFIM_EINVAL for a shape not valid for the handle's L. */
 int rfim_set_launch_shape(rfim_t *h, int mode, int nw, int wg);
 int rfim_get_launch_shape(const rfim_t *h, int *mode, int *nw, int *wg);
+
+/* Streams a streaming-mode half-sweep runs on (no effect on results).
+ * Replicas do not interact between exchange steps, so the library can run
+ * the half-sweeps of replicas [0, R/2) on the handle stream and those of
+ * [R/2, R) on a second stream it owns, forked from and joined back into the
+ * handle stream by events around every exchange interval; the two launch
+ * sequences then fill each other's start-up and drain time.  streams = 0:
+ * automatic (two streams when each half holds at least 2^22 sites of one
+ * colour), 1: always one stream, 2: two streams whenever R >= 2.  Only
+ * streaming shapes (mode 0, power-of-two L) are affected.  RFIM_EINVAL for
+ * other values. */
+int rfim_set_concurrency(rfim_t *h, int streams);
+int rfim_get_concurrency(const rfim_t *h);
 
 /* Checkpoint: the whole chain state (parameters, fields, temperatures,
  * spins, permutation, counters, exchange statistics) as a byte blob.

@@ -41,14 +41,14 @@ def halo_surface(w: int, x: float, y: float) -> float:
 def candidate_shapes(L: int) -> List[Tuple[int, int, int]]:
     """Valid (mode, dwords per thread, threads per workgroup) for L."""
     out = []
-    for nw in (1, 2, 4):
+    for nw in (1, 2, 4, 8):
         if 4 * nw > L // 2:
             continue
         chunks = L ** 3 // 8 // nw
         for wg in (64, 128, 256):
             if chunks % wg == 0 or chunks < wg:
                 out.append((0, nw, wg))
-        if L <= 32:
+        if L <= 32 and nw <= 4:
             for wg in (64, 128, 256, 512, 1024):
                 out.append((1, nw, wg))
     # wave64 analogue of the paper's rule: a wave covers a 64-site row

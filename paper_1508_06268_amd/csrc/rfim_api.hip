@@ -53,12 +53,15 @@ struct rfim {
     uint32_t rho = 0;
     std::vector<float> fields;      // natural order, as given
     std::vector<double> T;          // by slot
-    uint32_t always_mask = 0;
     // host mirrors of the device counters
     uint64_t t = 0, k = 0;
-    // stream
+    // stream; a second internal stream takes half of the replicas of large
+    // streaming sweeps (fork and join through events on the handle stream)
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int concurrency = 0;            // see rfim_set_concurrency
     // device memory
     uint8_t *d_spins = nullptr, *d_fbits = nullptr;
     float *d_fhf = nullptr, *d_fraw = nullptr, *d_betaf = nullptr;
@@ -92,7 +95,6 @@ struct rfim {
         a.key0 = (uint32_t)seed;
         a.key1 = (uint32_t)(seed >> 32);
         a.rho = rho;
-        a.always_mask = always_mask;
         a.spins = d_spins;
         a.fbits = d_fbits;
         a.fhf = d_fhf;
@@ -129,6 +131,9 @@ void free_device(rfim *h) {
     if (h->d_lat) (void)hipFree(h->d_lat);
     if (h->d_smap) (void)hipFree(h->d_smap);
     if (h->d_rmap) (void)hipFree(h->d_rmap);
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    if (h->aux) (void)hipStreamDestroy(h->aux);
 }
 
 int validate(const rfim_params_t *p, int *kind_out) {
@@ -169,7 +174,7 @@ int validate(const rfim_params_t *p, int *kind_out) {
 // b = 1 iff s_i = +1, f = 1 iff h_i = +1.  With s = 2b-1, the flip costs
 // dE = 2(J a + h c), a = s (2 up - 6) = s_i n_i, c = s (2f - 1) = s_i h_i.
 // FP64 on the host: thr = floor(exp(-beta dE) 2^32) clamped to 2^32 - 1;
-// entries with dE <= 0 are always accepted (marked in always_mask).
+// entries with dE <= 0 are always accepted.
 double index_delta(const rfim *h, int idx) {
     const int up = idx >> 2, b = (idx >> 1) & 1, f = idx & 1;
     const int s = 2 * b - 1;
@@ -182,21 +187,30 @@ int upload_tables(rfim *h) {
     std::vector<uint32_t> thr((size_t)h->R * 32, 0u);
     std::vector<double> beta(h->R);
     std::vector<float> betaf(h->R);
-    uint32_t mask = 0;
-    for (int idx = 0; idx < 28; ++idx)
-        if (index_delta(h, idx) <= 0.0) mask |= 1u << idx;
-    h->always_mask = mask;
+    // Accept iff dE <= 0 or u32 < floor(e^(-beta dE) 2^32) (clamped to
+    // 2^32 - 1), stored as "u32 <= entry": the bound minus one, all ones
+    // where dE <= 0, and a never bit in entry 31 where the bound is 0.
     for (int t = 0; t < h->R; ++t) {
         beta[t] = 1.0 / h->T[t];
         betaf[t] = (float)beta[t];
+        uint32_t never = 0;
         for (int idx = 0; idx < 28; ++idx) {
-            if (mask & (1u << idx)) {
-                thr[(size_t)t * 32 + idx] = 0xFFFFFFFFu;
+            uint32_t &e = thr[(size_t)t * 32 + idx];
+            const double dE = index_delta(h, idx);
+            if (dE <= 0.0) {
+                e = 0xFFFFFFFFu;
                 continue;
             }
-            const double scaled = std::ldexp(std::exp(-(beta[t] * index_delta(h, idx))), 32);
-            thr[(size_t)t * 32 + idx] = scaled >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)std::floor(scaled);
+            const double scaled = std::ldexp(std::exp(-(beta[t] * dE)), 32);
+            const uint32_t bound = scaled >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)std::floor(scaled);
+            if (bound == 0) {
+                never |= 1u << idx;
+                e = 0;
+            } else {
+                e = bound - 1u;
+            }
         }
+        thr[(size_t)t * 32 + 31] = never;
     }
     HIPCHK(hipMemcpyAsync(h->d_thr, thr.data(), thr.size() * 4, hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipMemcpyAsync(h->d_beta, beta.data(), beta.size() * 8, hipMemcpyHostToDevice, h->stream));
@@ -222,7 +236,7 @@ int alloc_device(rfim *h) {
     // partials buffer sized for the shape with the most workgroups
     int maxblk = 64;
     if (h->log2L >= 3) {
-        for (int nw : {1, 2, 4})
+        for (int nw : {1, 2, 4, 8})
             for (int wg : {64, 128, 256})
                 if (rfim_dev::shape_valid(h->L, 0, nw, wg))
                     maxblk = std::max(maxblk, rfim_dev::blocks_per_replica(h->L, 0, nw, wg));
@@ -259,7 +273,7 @@ int alloc_device(rfim *h) {
     ALLOC(h->d_rmap, Rc * sizeof(uint2));
     if (h->log2L >= 3) {
         size_t maxw = 1;
-        for (int nw : {1, 2, 4})
+        for (int nw : {1, 2, 4, 8})
             for (int wg : {64, 128, 256})
                 if (rfim_dev::shape_valid(h->L, 0, nw, wg))
                     maxw = std::max(maxw, (size_t)rfim_dev::stream_blocks_per_replica(h->L, nw, wg));
@@ -381,9 +395,12 @@ void default_shape(int L, int R, int *mode, int *nw, int *wg) {
         *wg = L == 8 ? 64 : 256;
         return;
     }
+    // measured on gfx950: 4 dwords in 128-thread groups at L >= 64 (whole
+    // rows of 8 dwords are no faster); one dword per thread in 256-thread
+    // groups at L = 32
     *mode = 0;
     *nw = L >= 64 ? 4 : 1;
-    *wg = L >= 64 ? 128 : 256;      // measured: 128-thread groups win at L=64
+    *wg = L >= 64 ? 128 : 256;
     (void)R;
 }
 
@@ -454,11 +471,38 @@ void destroy_impl(rfim *h) {
     delete h;
 }
 
+// Streaming sweeps of two halves of the replicas on two streams: replicas
+// never interact within an exchange interval, and the two launch sequences
+// fill each other's start-up and drain time.  Worth it only for launches
+// that are large on their own.
+constexpr long long kSplitMinAttempts = 1ll << 22;
+
+int ensure_aux(rfim *h) {
+    if (h->aux) return RFIM_OK;
+    HIPCHK(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+    return RFIM_OK;
+}
+
 int sweep_impl(rfim *h, int64_t n, int every) {
     h->lat_host = h->lattice();
     const Lattice &lat = h->lat_host;
     const rfim_dev::Launch ln = single_launch(h);
     const bool pow2 = h->log2L >= 3;
+    const bool big = (long long)(h->R / 2) * h->half >= kSplitMinAttempts;
+    const bool split = pow2 && h->mode == 0 && h->R >= 2 &&
+                       (h->concurrency == 2 || (h->concurrency == 0 && big));
+    rfim_dev::Launch la = ln, lb = ln;
+    if (split) {
+        int rc;
+        if ((rc = ensure_aux(h))) return rc;
+        const int wpr = ln.nblocks / h->R;
+        const int ra = h->R / 2;
+        la.nblocks = ra * wpr;
+        lb.r0 = ra;
+        lb.nblocks = (h->R - ra) * wpr;
+    }
     int64_t remaining = n;
     while (remaining > 0) {
         int64_t to_next = every > 0 ? (int64_t)(every - (int64_t)(h->t % (uint64_t)every)) : remaining;
@@ -467,6 +511,18 @@ int sweep_impl(rfim *h, int64_t n, int every) {
         const bool fused = exch && rfim_dev::fused_energy(lat);
         if (pow2 && h->mode == 1) {
             HIPCHK(rfim_dev::launch_resident(ln, m, fused ? 1 : 0, h->stream));
+        } else if (pow2 && split) {
+            HIPCHK(hipEventRecord(h->ev_fork, h->stream));
+            HIPCHK(hipStreamWaitEvent(h->aux, h->ev_fork, 0));
+            for (int q = 0; q < m; ++q) {
+                const int e = fused && q == m - 1;
+                HIPCHK(rfim_dev::launch_stream_sweep(la, 0, q, 0, h->stream));
+                HIPCHK(rfim_dev::launch_stream_sweep(lb, 0, q, 0, h->aux));
+                HIPCHK(rfim_dev::launch_stream_sweep(la, 1, q, e, h->stream));
+                HIPCHK(rfim_dev::launch_stream_sweep(lb, 1, q, e, h->aux));
+            }
+            HIPCHK(hipEventRecord(h->ev_join, h->aux));
+            HIPCHK(hipStreamWaitEvent(h->stream, h->ev_join, 0));
         } else if (pow2) {
             for (int q = 0; q < m; ++q) {
                 HIPCHK(rfim_dev::launch_stream_sweep(ln, 0, q, 0, h->stream));
@@ -806,6 +862,18 @@ int rfim_get_launch_shape(const rfim_t *h, int *mode, int *nw, int *wg) {
     *nw = h->nw;
     *wg = h->wg;
     return RFIM_OK;
+}
+
+int rfim_set_concurrency(rfim_t *h, int streams) {
+    if (!h) return fail(RFIM_EINVAL, "handle is NULL");
+    if (streams < 0 || streams > 2) return fail(RFIM_EINVAL, "streams must be 0, 1 or 2 (got %d)", streams);
+    h->concurrency = streams;
+    return RFIM_OK;
+}
+
+int rfim_get_concurrency(const rfim_t *h) {
+    if (!h) return fail(RFIM_EINVAL, "handle is NULL");
+    return h->concurrency;
 }
 
 // ---- checkpoint ----------------------------------------------------
@@ -1265,7 +1333,7 @@ size_t device_bytes(int L, int R_cap, int kind) {
     size_t maxblk = 64, maxw = 1;
     const bool pow2 = L >= 8 && (L & (L - 1)) == 0;
     if (pow2)
-        for (int nw : {1, 2, 4})
+        for (int nw : {1, 2, 4, 8})
             for (int wg : {64, 128, 256})
                 if (rfim_dev::shape_valid(L, 0, nw, wg)) {
                     maxblk = std::max(maxblk, (size_t)rfim_dev::blocks_per_replica(L, 0, nw, wg));

@@ -14,10 +14,14 @@ namespace rfim_dev {
 //   fbits  uint8 [2][N/2]         +-1 fields: byte = 4 iff h_i = +1, else 0.
 //   fhf    float [2][N/2]         continuous fields: (float)(h * h_i - 6 J).
 //   fraw   float [2][N/2]         continuous fields: h_i as given.
-//   thr    uint32 [R_cap][32]     per slot, +-1 fields: threshold indexed by
+//   thr    uint32 [R_cap][32]     per slot, +-1 fields, indexed by
 //                                 (up << 2) | (b << 1) | f with up = number of
-//                                 +1 neighbours, b = spin byte, f = field bit;
-//                                 0xFFFFFFFF where dE <= 0 (always accepted).
+//                                 +1 neighbours, b = spin byte, f = field bit:
+//                                 a flip is taken iff u32 <= entry, unless bit
+//                                 idx of entry 31 (the slot's never mask) is
+//                                 set.  Entry = 0xFFFFFFFF where dE <= 0,
+//                                 else floor(e^(-beta dE) 2^32) - 1, or 0 with
+//                                 the never bit where that floor is 0.
 //   betaf  float [R_cap]          per slot, continuous fields.
 //   beta   double [R_cap]         per slot (exchange).
 //   t2r, r2t int32 [R_cap]; att, acc uint64 [R_cap]
@@ -36,7 +40,6 @@ struct Lattice {
     float Jf;
     double J, h;
     uint32_t key0, key1, rho;
-    uint32_t always_mask;       // bit ((up << 2) | (b << 1) | f) set iff dE <= 0
     uint8_t *spins;
     const uint8_t *fbits;
     const float *fhf, *fraw;
@@ -83,8 +86,9 @@ struct Launch {
     int nblocks;
     int L, kind, mode, nw, wg;
     // one realization: its descriptor, passed by value (lats and map
-    // unused; blocks enumerate (replica, block) in order)
+    // unused; blocks enumerate (replica, block) in order, from replica r0)
     const Lattice *single = nullptr;
+    int r0 = 0;
 };
 
 hipError_t launch_init(const Lattice &lat, int r0, int r1, hipStream_t s);

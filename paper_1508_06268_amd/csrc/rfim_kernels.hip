@@ -51,8 +51,8 @@ __device__ __forceinline__ Words philox10(uint32_t c0, uint32_t c1, uint32_t c2,
         if (round < 2) {
             // the first rounds still hold wave-uniform words: leave them to
             // the scalar unit
-            n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
-            n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+            n0 = (uint32_t)(b >> 32) ^ (c1 ^ k0);
+            n2 = (uint32_t)(a >> 32) ^ (c3 ^ k1);
         } else {
             // three-input XOR in one VALU instruction (truth table 0x96)
             n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(b >> 32), c1, k0, 0x96);
@@ -144,7 +144,8 @@ __global__ __launch_bounds__(256) void sweep_generic(Lattice lat, int colour, in
         if (KIND == 0) {
             const int f = lat.fbits[(size_t)colour * lat.half + j] >> 2;
             const int idx = (up << 2) | (b << 1) | f;
-            accept = ((lat.always_mask >> idx) & 1u) || u < lat.thr[slot * 32 + idx];
+            const uint32_t *tab = lat.thr + slot * 32;
+            accept = u <= tab[idx] && !((tab[31] >> idx) & 1u);
         } else {
             const float a = -2.0f * 1.44269504088896341f * lat.betaf[slot];
             accept = cont_accept((float)up, lat.fhf[(size_t)colour * lat.half + j], 2.0f * lat.Jf, a, b != 0, u);
@@ -176,6 +177,18 @@ template <> struct Vec<4> { using T = u32x4; };
 
 template <int NW, class P>
 __device__ __forceinline__ void load_words(P base, uint32_t off, uint32_t (&w)[NW]) {
+    if constexpr (NW == 8) {
+        // two 16-byte loads
+        uint32_t lo[4], hi[4];
+        load_words<4>(base, off, lo);
+        load_words<4>(base, off + 16u, hi);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            w[q] = lo[q];
+            w[q + 4] = hi[q];
+        }
+        return;
+    } else {
     const typename Vec<NW>::T v = *(typename rebind_ptr<P, const typename Vec<NW>::T>::type)(base + off);
     if constexpr (NW == 1) {
         w[0] = v;
@@ -184,10 +197,17 @@ __device__ __forceinline__ void load_words(P base, uint32_t off, uint32_t (&w)[N
     } else {
         w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
     }
+    }
 }
 
 template <int NW, class P>
 __device__ __forceinline__ void store_words(P base, uint32_t off, const uint32_t (&w)[NW]) {
+    if constexpr (NW == 8) {
+        const uint32_t lo[4] = {w[0], w[1], w[2], w[3]}, hi[4] = {w[4], w[5], w[6], w[7]};
+        store_words<4>(base, off, lo);
+        store_words<4>(base, off + 16u, hi);
+        return;
+    } else {
     typename Vec<NW>::T v;
     if constexpr (NW == 1) {
         v = w[0];
@@ -197,6 +217,7 @@ __device__ __forceinline__ void store_words(P base, uint32_t off, const uint32_t
         v.x = w[0]; v.y = w[1]; v.z = w[2]; v.w = w[3];
     }
     *(typename rebind_ptr<P, typename Vec<NW>::T>::type)(base + off) = v;
+    }
 }
 
 __device__ __forceinline__ int wave_isum(int v) {
@@ -248,35 +269,69 @@ __device__ __forceinline__ void neighbour_counts(P oth, uint32_t j0, const Chunk
     load_words<NW>(oth, c.jym, Wym);
     load_words<NW>(oth, c.jzp, Wzp);
     load_words<NW>(oth, c.jzm, Wzm);
+    // p = 1: bytes of pairs m+1..m+4 (bytes 1-3 of W[w], byte 0 of the next
+    // word); p = 0: bytes of pairs m-1..m+2 (byte 3 of the previous word,
+    // bytes 0-2 of W[w]).  One byte permute of {other word, W[w]}.
+    const uint32_t sel = c.p ? 0x04030201u : 0x02010007u;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
-        // p = 1: bytes of pairs m+1..m+4; p = 0: bytes of pairs m-1..m+2
         const uint32_t nxt = (w + 1 < NW) ? W[w + 1 < NW ? w + 1 : 0] : Wx;
         const uint32_t prv = (w > 0) ? W[w > 0 ? w - 1 : 0] : Wx;
-        const uint32_t Xs = c.p ? __builtin_amdgcn_alignbyte(nxt, W[w], 1) : __builtin_amdgcn_alignbyte(W[w], prv, 3);
+        const uint32_t Xs = __builtin_amdgcn_perm(c.p ? nxt : prv, W[w], sel);
         U[w] = W[w] + Xs + Wyp[w] + Wym[w] + Wzp[w] + Wzm[w];
     }
 }
 
+// Bit q set iff u_q <= t_q, for four sites.  The compares write four lane
+// masks that an add-with-carry chain folds into one register (acc = 2 acc +
+// mask), so each site costs two VALU instructions and no select.  gfx950
+// wants two wait states between a VALU write of a lane mask and a VALU read
+// of it: every mask is read three instructions after it is written, and the
+// trailing nop covers reads after the block.
+__device__ __forceinline__ uint32_t accept_bits(uint32_t u0, uint32_t u1, uint32_t u2, uint32_t u3,
+                                                uint32_t t0, uint32_t t1, uint32_t t2, uint32_t t3) {
+    uint32_t acc;
+    uint64_t c3, c2, c1, c0, cx;
+    asm("v_cmp_le_u32_e64 %1, %9, %13\n\t"
+        "v_cmp_le_u32_e64 %2, %8, %12\n\t"
+        "v_cmp_le_u32_e64 %3, %7, %11\n\t"
+        "v_cmp_le_u32_e64 %4, %6, %10\n\t"
+        "v_cndmask_b32_e64 %0, 0, 1, %1\n\t"
+        "v_addc_co_u32_e64 %0, %5, %0, %0, %2\n\t"
+        "v_addc_co_u32_e64 %0, %5, %0, %0, %3\n\t"
+        "v_addc_co_u32_e64 %0, %5, %0, %0, %4\n\t"
+        "s_nop 1"
+        : "=&v"(acc), "=&s"(c3), "=&s"(c2), "=&s"(c1), "=&s"(c0), "=&s"(cx)
+        : "v"(u0), "v"(u1), "v"(u2), "v"(u3), "v"(t0), "v"(t1), "v"(t2), "v"(t3));
+    return acc;
+}
+
 // Metropolis decisions of one Philox block's four sites (+-1 fields): the
-// threshold sits at LDS byte address ((up << 2) | (s << 1) | f) * 4.
+// table entry sits at LDS byte address ((up << 2) | (s << 1) | f) * 4 and a
+// site flips iff u <= entry.  `never` marks classes whose bound is 0 at this
+// temperature: there u = 0 would pass, so with NEV those sites are
+// corrected when some u is 0 (about one block in 2^30).  Returns the flips
+// as one bit per byte.
+template <bool NEV>
 __device__ __forceinline__ uint32_t bimodal_flips(const uint32_t *sthr, uint32_t U, uint32_t Wown,
-                                                  uint32_t F4, const Words &rw, uint32_t always_mask) {
+                                                  uint32_t F4, const Words &rw, uint32_t never) {
     const uint32_t A = (U << 4) | (Wown << 3) | F4;
     const uint8_t *tb = (const uint8_t *)sthr;
     const uint32_t a0 = A & 0xFFu, a1 = (A >> 8) & 0xFFu, a2 = (A >> 16) & 0xFFu, a3 = A >> 24;
     const uint32_t th0 = *(const uint32_t *)(tb + a0), th1 = *(const uint32_t *)(tb + a1);
     const uint32_t th2 = *(const uint32_t *)(tb + a2), th3 = *(const uint32_t *)(tb + a3);
-    uint32_t fl = (rw.w0 < th0 ? 0x1u : 0u) | (rw.w1 < th1 ? 0x100u : 0u) |
-                  (rw.w2 < th2 ? 0x10000u : 0u) | (rw.w3 < th3 ? 0x1000000u : 0u);
-    // A word of 0xFFFFFFFF fails "u < thr" even where dE <= 0, which always
-    // flips: fix those up (about one block in 2^30).
-    const uint32_t umax = max(max(rw.w0, rw.w1), max(rw.w2, rw.w3));
-    if (umax == 0xFFFFFFFFu) {
-        if (rw.w0 == 0xFFFFFFFFu && ((always_mask >> (a0 >> 2)) & 1u)) fl |= 0x1u;
-        if (rw.w1 == 0xFFFFFFFFu && ((always_mask >> (a1 >> 2)) & 1u)) fl |= 0x100u;
-        if (rw.w2 == 0xFFFFFFFFu && ((always_mask >> (a2 >> 2)) & 1u)) fl |= 0x10000u;
-        if (rw.w3 == 0xFFFFFFFFu && ((always_mask >> (a3 >> 2)) & 1u)) fl |= 0x1000000u;
+    const uint32_t acc = accept_bits(rw.w0, rw.w1, rw.w2, rw.w3, th0, th1, th2, th3);
+    // bit q of a 4-bit value to bit 8q: the shifted copies 0, 7, 14, 21
+    // do not overlap, so the product has no carries
+    uint32_t fl = __umul24(acc, 0x204081u) & 0x01010101u;
+    if (NEV) {
+        const uint32_t umin = min(min(rw.w0, rw.w1), min(rw.w2, rw.w3));
+        if (umin == 0u) {
+            if (rw.w0 == 0u && ((never >> (a0 >> 2)) & 1u)) fl &= ~0x1u;
+            if (rw.w1 == 0u && ((never >> (a1 >> 2)) & 1u)) fl &= ~0x100u;
+            if (rw.w2 == 0u && ((never >> (a2 >> 2)) & 1u)) fl &= ~0x10000u;
+            if (rw.w3 == 0u && ((never >> (a3 >> 2)) & 1u)) fl &= ~0x1000000u;
+        }
     }
     return fl;
 }
@@ -296,8 +351,9 @@ __device__ __forceinline__ uint32_t continuous_flips(uint32_t U, uint32_t Wown, 
 
 // One chunk's half-sweep update; returns the new own words (and the loaded
 // words the energy pass reuses).
-template <int KIND, int NW, class PO, class PC, class PB, class PF>
-__device__ __forceinline__ uint32_t chunk_update(const Lattice &lat, const uint32_t *sthr, PO own, PC oth,
+template <int KIND, int NW, bool NEV, class PO, class PC, class PB, class PF>
+__device__ __forceinline__ uint32_t chunk_update(const Lattice &lat, const uint32_t *sthr, uint32_t never,
+                                                 PO own, PC oth,
                                                  PB fb_own, PF hf_own, uint32_t j0, uint32_t g0,
                                                  uint32_t colour, uint32_t c1, uint32_t r, float beta,
                                                  uint32_t (&W)[NW], uint32_t (&U)[NW],
@@ -314,7 +370,7 @@ __device__ __forceinline__ uint32_t chunk_update(const Lattice &lat, const uint3
         const Words rw = philox10(g0 + (uint32_t)w, c1, r, c3, lat.key0, lat.key1);
         uint32_t fl;
         if (KIND == 0) {
-            fl = bimodal_flips(sthr, U[w], Wown[w], F4[w], rw, lat.always_mask);
+            fl = bimodal_flips<NEV>(sthr, U[w], Wown[w], F4[w], rw, never);
         } else {
             const f32x4 hf = *(typename rebind_ptr<PF, const f32x4>::type)(hf_own + j0 + 4u * w);
             fl = continuous_flips(U[w], Wown[w], hf, 2.0f * lat.Jf, -2.0f * 1.44269504088896341f * beta, rw);
@@ -323,6 +379,21 @@ __device__ __forceinline__ uint32_t chunk_update(const Lattice &lat, const uint3
         Wnew[w] = Wown[w] ^ fl;
     }
     return any;
+}
+
+// chunk_update with the never-class correction only where this slot has
+// such classes (a wave-uniform branch between two copies).
+template <int KIND, int NW, class PO, class PC, class PB, class PF>
+__device__ __forceinline__ uint32_t chunk_update_any(const Lattice &lat, const uint32_t *sthr, uint32_t never,
+                                                     PO own, PC oth, PB fb_own, PF hf_own, uint32_t j0,
+                                                     uint32_t g0, uint32_t colour, uint32_t c1, uint32_t r,
+                                                     float beta, uint32_t (&W)[NW], uint32_t (&U)[NW],
+                                                     uint32_t (&Wnew)[NW], uint32_t (&F4)[NW]) {
+    if (KIND == 0 && never != 0u)
+        return chunk_update<KIND, NW, true>(lat, sthr, never, own, oth, fb_own, hf_own, j0, g0, colour, c1, r,
+                                            beta, W, U, Wnew, F4);
+    return chunk_update<KIND, NW, false>(lat, sthr, never, own, oth, fb_own, hf_own, j0, g0, colour, c1, r,
+                                         beta, W, U, Wnew, F4);
 }
 
 // Energy pieces of a chunk of colour-1 sites and the colour-0 sites of the
@@ -386,12 +457,13 @@ __device__ __forceinline__ void block_partial(PD dst, int nsite, int ksum, int u
 
 // Streaming half-sweep: one chunk per thread; one launch covers every
 // replica of every realization listed in the block map (entry: realization,
-// (replica << 16) | block within the replica).  ENERGY (colour 1 of the last
+// (replica << 16) | block within the replica), or, for one realization,
+// replicas r0, r0 + 1, ... in block order.  ENERGY (colour 1 of the last
 // sweep before an exchange) also writes one energy partial per workgroup.
 template <int KIND, int NW, int ENERGY, bool BATCH>
 __global__ __launch_bounds__(256) void sweep_pow2(Lattice lat0, const Lattice *__restrict__ lats,
                                                    const uint2 *__restrict__ map, int colour, int toff,
-                                                   int remap, int wpr) {
+                                                   int remap, int lwpr, int r0) {
     __shared__ uint32_t sthr[32];
     uint32_t blk = blockIdx.x;
     if (remap) {
@@ -406,14 +478,16 @@ __global__ __launch_bounds__(256) void sweep_pow2(Lattice lat0, const Lattice *_
         r = e.x & 0xFFFFu;
         gb = e.y;
     } else {
-        r = blk / (uint32_t)wpr;
-        gb = blk - r * (uint32_t)wpr;
+        r = (uint32_t)r0 + (blk >> lwpr);
+        gb = blk & ((1u << lwpr) - 1u);
     }
     const Lattice &lat = BATCH ? lats[map[blk].x >> 16] : lat0;
     const int slot = gptr(lat.r2t)[r];
+    uint32_t never = 0;
     if (KIND == 0) {
         if (threadIdx.x < 32) sthr[threadIdx.x] = gptr(lat.thr)[slot * 32 + threadIdx.x];
         __syncthreads();
+        never = __builtin_amdgcn_readfirstlane(sthr[31]);
     }
     const uint32_t g0 = (gb * blockDim.x + threadIdx.x) * NW;   // first Philox block
     const uint32_t j0 = 4u * g0;
@@ -426,7 +500,7 @@ __global__ __launch_bounds__(256) void sweep_pow2(Lattice lat0, const Lattice *_
     const uint32_t t = (uint32_t)(gptr(lat.ctrs)[0] + (uint64_t)toff);
     const float beta = KIND == 1 ? gptr(lat.betaf)[slot] : 0.0f;
     uint32_t W[NW], U[NW], Wnew[NW], F4[NW];
-    const uint32_t any = chunk_update<KIND, NW>(lat, sthr, own, oth, fbits + (size_t)col * lat.half,
+    const uint32_t any = chunk_update_any<KIND, NW>(lat, sthr, never, own, oth, fbits + (size_t)col * lat.half,
                                                 fhf + (size_t)col * lat.half, j0, g0, col, 2u * t + col, r,
                                                 beta, W, U, Wnew, F4);
     if (any) store_words<NW>(own, j0, Wnew);
@@ -467,6 +541,7 @@ __global__ __launch_bounds__(1024) void sweep_resident(Lattice lat0, const Latti
     GAS const float *fhf = gptr(lat.fhf), *fraw = gptr(lat.fraw);
     const uint32_t nchunk = half / (4u * NW);
     __syncthreads();
+    const uint32_t never = KIND == 0 ? __builtin_amdgcn_readfirstlane(sthr[31]) : 0u;
     for (int sw = 0; sw < nsweep; ++sw) {
         for (uint32_t col = 0; col < 2; ++col) {
             uint8_t *own = sp + col * half;
@@ -475,7 +550,7 @@ __global__ __launch_bounds__(1024) void sweep_resident(Lattice lat0, const Latti
             for (uint32_t ch = threadIdx.x; ch < nchunk; ch += blockDim.x) {
                 const uint32_t g0 = ch * NW, j0 = 4u * g0;
                 uint32_t W[NW], U[NW], Wnew[NW], F4[NW];
-                const uint32_t any = chunk_update<KIND, NW>(lat, sthr, own, oth, fbits + (size_t)col * half,
+                const uint32_t any = chunk_update_any<KIND, NW>(lat, sthr, never, own, oth, fbits + (size_t)col * half,
                                                             fhf + (size_t)col * half, j0, g0, col, c1, r, beta,
                                                             W, U, Wnew, F4);
                 if (any) store_words<NW>(own, j0, Wnew);
@@ -648,7 +723,7 @@ __global__ void advance_kernel(uint64_t *ctrs, int tadv) {
 bool shape_valid(int L, int mode, int nw, int wg) {
     const bool pow2 = L >= 8 && (L & (L - 1)) == 0;
     if (!pow2) return mode == 0 && nw == 0 && wg == 0;      // generic kernel, fixed shape
-    if (nw != 1 && nw != 2 && nw != 4) return false;
+    if (nw != 1 && nw != 2 && nw != 4 && nw != 8) return false;
     if (4 * nw > L / 2) return false;                        // a chunk lies inside one row
     const long long chunks = (long long)L * L * L / 8 / nw;  // per colour and replica
     if (mode == 0) {
@@ -656,7 +731,7 @@ bool shape_valid(int L, int mode, int nw, int wg) {
         return chunks % wg == 0 || chunks < wg;
     }
     if (mode == 1) {
-        if (L > 32) return false;                            // one replica must fit in LDS
+        if (L > 32 || nw > 4) return false;                  // one replica must fit in LDS
         return wg == 64 || wg == 128 || wg == 256 || wg == 512 || wg == 1024;
     }
     return false;
@@ -706,17 +781,20 @@ static void launch_pow2(const Launch &ln, const Lattice &lat0, int colour, int t
     // a block must own a chunk of that replica
     const long long chunks = (long long)ln.L * ln.L * ln.L / 8 / ln.nw;
     const int wg = chunks < ln.wg ? (int)chunks : ln.wg;
-    const int wpr = (int)(chunks / wg);
+    const int lwpr = __builtin_ctzll((unsigned long long)(chunks / wg));   // a power of two
     const dim3 grid(ln.nblocks), block(wg);
-    if (ln.nw == 4)
+    if (ln.nw == 8)
+        hipLaunchKernelGGL((sweep_pow2<KIND, 8, ENERGY, BATCH>), grid, block, 0, s, lat0, ln.lats, ln.map, colour,
+                           toff, remap, lwpr, ln.r0);
+    else if (ln.nw == 4)
         hipLaunchKernelGGL((sweep_pow2<KIND, 4, ENERGY, BATCH>), grid, block, 0, s, lat0, ln.lats, ln.map, colour,
-                           toff, remap, wpr);
+                           toff, remap, lwpr, ln.r0);
     else if (ln.nw == 2)
         hipLaunchKernelGGL((sweep_pow2<KIND, 2, ENERGY, BATCH>), grid, block, 0, s, lat0, ln.lats, ln.map, colour,
-                           toff, remap, wpr);
+                           toff, remap, lwpr, ln.r0);
     else
         hipLaunchKernelGGL((sweep_pow2<KIND, 1, ENERGY, BATCH>), grid, block, 0, s, lat0, ln.lats, ln.map, colour,
-                           toff, remap, wpr);
+                           toff, remap, lwpr, ln.r0);
 }
 
 template <int KIND, bool BATCH>

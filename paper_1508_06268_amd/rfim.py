@@ -27,7 +27,8 @@ EXPORTS = [
     "rfim_magnetizations", "rfim_components", "rfim_get_spins", "rfim_set_spins",
     "rfim_get_perm", "rfim_set_perm", "rfim_get_counters", "rfim_set_counters",
     "rfim_exchange_stats", "rfim_reset_exchange_stats", "rfim_save", "rfim_load",
-    "rfim_set_launch_shape", "rfim_get_launch_shape", "rfim_observables", "rfim_reset_observables",
+    "rfim_set_launch_shape", "rfim_get_launch_shape", "rfim_set_concurrency", "rfim_get_concurrency",
+    "rfim_observables", "rfim_reset_observables",
     "rfim_batch_create", "rfim_batch_destroy", "rfim_batch_size", "rfim_batch_sweep",
     "rfim_batch_synchronize", "rfim_batch_item", "rfim_batch_set_shape",
     "rfim_pool_create", "rfim_pool_destroy", "rfim_pool_bytes_needed", "rfim_pool_admit",
@@ -93,6 +94,8 @@ def load_library(path: str = LIB_PATH):
         "rfim_load": (vp, [vp, sz, vp]),
         "rfim_set_launch_shape": (i32, [vp, i32, i32, i32]),
         "rfim_get_launch_shape": (i32, [vp, vp, vp, vp]),
+        "rfim_set_concurrency": (i32, [vp, i32]),
+        "rfim_get_concurrency": (i32, [vp]),
         "rfim_observables": (i32, [vp, vp]),
         "rfim_reset_observables": (i32, [vp]),
         "rfim_batch_create": (vp, [i32, vp, vp]),
@@ -318,6 +321,13 @@ class Rfim:
 
     def set_launch_shape(self, mode, nw, wg):
         _check(load_library().rfim_set_launch_shape(self._h, int(mode), int(nw), int(wg)))
+
+    def concurrency(self) -> int:
+        return _check(load_library().rfim_get_concurrency(self._h))
+
+    def set_concurrency(self, streams: int):
+        """0 automatic, 1 one stream, 2 two streams (see rfim_set_concurrency)."""
+        _check(load_library().rfim_set_concurrency(self._h, int(streams)))
 
     def save(self) -> bytes:
         n = C.c_size_t(0)

@@ -57,3 +57,12 @@ def test_null_handle_calls_fail_cleanly(rfim_mod):
     assert lib.rfim_sweep(None, 1, 1) == -1
     assert lib.rfim_energies(None, None) == -1
     lib.rfim_destroy(None)
+
+
+def test_null_handle_getters_and_setters_fail_cleanly(rfim_mod):
+    lib = rfim_mod.load_library()
+    assert lib.rfim_set_concurrency(None, 0) == -1
+    assert lib.rfim_get_concurrency(None) == -1
+    assert lib.rfim_set_launch_shape(None, 0, 4, 128) == -1
+    assert lib.rfim_num_replicas(None) == -1
+    assert b"NULL" in lib.rfim_last_error()

@@ -28,7 +28,7 @@ def test_candidate_shapes():
         shapes = autotune.candidate_shapes(L)
         assert shapes, L
         for mode, nw, wg in shapes:
-            assert nw in (1, 2, 4) and 4 * nw <= L // 2
+            assert nw in (1, 2, 4, 8) and 4 * nw <= L // 2
             assert mode in (0, 1)
             if mode == 1:
                 assert L <= 32

@@ -116,7 +116,7 @@ SHAPES = {
     8: [(0, 1, 64), (1, 1, 64), (1, 1, 256), (0, 1, 256)],
     16: [(0, 1, 256), (0, 2, 128), (1, 2, 256), (1, 1, 1024), (1, 2, 64)],
     32: [(0, 4, 256), (0, 1, 64), (0, 2, 128), (1, 4, 1024), (1, 2, 512), (1, 1, 256)],
-    64: [(0, 4, 256), (0, 2, 128), (0, 1, 64), (0, 4, 64)],
+    64: [(0, 4, 256), (0, 2, 128), (0, 1, 64), (0, 4, 64), (0, 8, 64), (0, 8, 128), (0, 8, 256)],
 }
 
 
@@ -187,3 +187,65 @@ def test_observables_match_oracle_replay(rfim_mod, oracle_mod):
     assert np.array_equal(g.observables(), want)
     g.reset_observables()
     assert not g.observables().any()
+
+
+# Seeds whose sweep stream holds a zero word early: (L, seed, sweep t,
+# colour, replica, sublattice j).  Found by scanning seeds with the oracle's
+# Philox; tests/test_oracle_rng_mapping.py pins that the word is zero and
+# that it lands on a class that must never flip at these temperatures.
+ZERO_WORD_CASES = [(8, 4320, 153, 0, 0, 205), (6, 8188, 225, 0, 2, 2)]
+FROZEN_TEMPS = [0.05, 0.06, 0.07, 0.08]
+
+
+@pytest.mark.parametrize("L,seed,t,c,r,j", ZERO_WORD_CASES)
+def test_zero_word_on_a_never_class(rfim_mod, oracle_mod, L, seed, t, c, r, j):
+    """At these temperatures every class with dE > 0 has bound 0 (never
+    flips), but the device compares u <= bound - 1 with a per-slot never
+    mask: a zero word on such a site must still be refused.  The state is
+    compared right after sweep t (the next sweep would undo the flip)."""
+    f = W.bimodal_fields(L, [7, L, 0])
+    T = np.array(FROZEN_TEMPS)
+    o = oracle_mod.Oracle(L, 4, 1.0, 1.0, f, T, seed=seed)
+    o.sweep(t + 1, 10)
+    shapes = SHAPES.get(L, [None])
+    for shape in shapes:
+        g = rfim_mod.Rfim(L, 4, 1.0, 1.0, f, T, seed=seed)
+        if shape is not None:
+            g.set_launch_shape(*shape)
+        g.sweep(t + 1, 10)
+        assert_same_state(g, o, "L=%d shape %s" % (L, shape))
+        g.close()
+
+
+@pytest.mark.parametrize("shape", [(0, 4, 128), (0, 8, 128)])
+def test_two_stream_split_matches_oracle(rfim_mod, oracle_mod, shape):
+    """L=64 with enough replicas that a half-sweep is split over two streams
+    (replicas [0, R/2) and [R/2, R)): same chain as the oracle, bit for bit,
+    across exchange steps and a ragged interval."""
+    L, R = 64, 64
+    f = W.bimodal_fields(L, [19, L])
+    T = W.linear_temps(R, 1.0, 6.0)
+    g, o = make_pair(rfim_mod, oracle_mod, L, R, 1.0, 2.25, f, T, seed=99)
+    g.set_launch_shape(*shape)
+    g.sweep(13, 5)
+    o.sweep(13, 5)
+    assert_same_state(g, o, "L=64 R=64 split, shape %s" % (shape,))
+    g.close()
+
+
+def test_forced_split_small_lattice(rfim_mod, oracle_mod):
+    """Two streams forced on a small streaming lattice (odd R: halves of 3
+    and 4 replicas): still the oracle's chain; invalid stream counts are
+    refused."""
+    L, R = 32, 7
+    f = W.bimodal_fields(L, [23, L])
+    T = W.linear_temps(R, 1.0, 5.0)
+    g, o = make_pair(rfim_mod, oracle_mod, L, R, 1.0, 1.5, f, T, seed=5)
+    g.set_concurrency(2)
+    assert g.concurrency() == 2
+    g.sweep(17, 4)
+    o.sweep(17, 4)
+    assert_same_state(g, o, "L=32 R=7 two streams")
+    with pytest.raises(rfim_mod.RfimError):
+        g.set_concurrency(3)
+    g.close()

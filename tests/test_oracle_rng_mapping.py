@@ -89,3 +89,30 @@ def test_sweep_replay_and_strict_boundary(oracle_mod):
             # a colour-0 site is not touched again by the colour-1 half-sweep
             assert (after[ii] != s0[ii]) == acc, (jj, ii)
         assert (after[i] != s0[i]) == flips
+
+
+ZERO_WORD_CASES = [(8, 4320, 153, 0, 0, 205), (6, 8188, 225, 0, 2, 2)]
+
+
+def test_zero_words_land_on_never_classes(oracle_mod):
+    """The seeds the GPU never-class test uses: the sweep word of (t, c, r,
+    j) is 0, and at the frozen temperatures that site's move is uphill with
+    threshold 0, so "u < threshold" refuses it even for u = 0."""
+    for L, seed, t, c, r, j in ZERO_WORD_CASES:
+        assert int(_words(oracle_mod, seed, j >> 2, 2 * t + c, r, TAG_SWEEP)[j & 3]) == 0
+        f = W.bimodal_fields(L, [7, L, 0])
+        o = oracle_mod.Oracle(L, 4, 1.0, 1.0, f, [0.05, 0.06, 0.07, 0.08], seed=seed)
+        o.sweep(t, 10)
+        i0 = 2 * j
+        z, y, x = i0 // (L * L), (i0 // L) % L, i0 % L
+        i = i0 if (x + y + z) % 2 == c else i0 + 1
+        before = o.spins()[r, i]
+        dE = o.flip_delta(r, i)
+        assert dE > 0
+        thr, always = o.thresholds()
+        slot = int(np.argwhere(o.perm() == r)[0, 0])
+        s_lat, f_lat = lattice(o.spins()[r], L), lattice(f, L)
+        cls = _site_class(s_lat, f_lat, i // (L * L), (i // L) % L, i % L)
+        assert not always[cls] and int(thr[slot, cls]) == 0
+        o.sweep(1, 10)
+        assert o.spins()[r, i] == before
