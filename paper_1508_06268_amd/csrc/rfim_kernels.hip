@@ -336,17 +336,39 @@ __device__ __forceinline__ uint32_t bimodal_flips(const uint32_t *sthr, uint32_t
     return fl;
 }
 
-// Continuous fields: four sites of one Philox block (see cont_accept).
+// Float to unsigned integer with the hardware's saturation (values at or
+// above 2^32, infinity included, give 0xFFFFFFFF; negative values give 0).
+__device__ __forceinline__ uint32_t cvt_u32_sat(float x) {
+    uint32_t r;
+    asm("v_cvt_u32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+// Continuous fields, one site of a packed word: the integer bound
+// floor(e^(-beta dE) 2^32), saturated, with e^(-beta dE) = 2^(s a y)
+// (a = -2 beta log2(e), y as in cont_accept, s = 2 spin - 1 taken as
+// a (2 spin - 1) by one fma).  dE <= 0 gives a power >= 1 and the bound
+// 0xFFFFFFFF, which every u32 meets: one integer test u <= bound covers
+// both cases of the Metropolis rule.
+__device__ __forceinline__ uint32_t cont_bound(float up, float spin, float hfs, float twoJ, float a) {
+    const float y = fmaf(twoJ, up, hfs);
+    const float sa = fmaf(2.0f * a, spin, -a);
+    const float p = __builtin_amdgcn_exp2f(sa * y);
+    return cvt_u32_sat(p * 0x1p32f);
+}
+
+// Continuous fields: four sites of one Philox block.
 __device__ __forceinline__ uint32_t continuous_flips(uint32_t U, uint32_t Wown, const f32x4 hf, float twoJ,
                                                      float a, const Words &rw) {
     // byte-to-float conversions (one v_cvt_f32_ubyteN each)
     const float up0 = (float)(U & 0xFFu), up1 = (float)((U >> 8) & 0xFFu);
     const float up2 = (float)((U >> 16) & 0xFFu), up3 = (float)(U >> 24);
-    uint32_t fl = cont_accept(up0, hf.x, twoJ, a, Wown & 0x1u, rw.w0) ? 0x1u : 0u;
-    fl |= cont_accept(up1, hf.y, twoJ, a, Wown & 0x100u, rw.w1) ? 0x100u : 0u;
-    fl |= cont_accept(up2, hf.z, twoJ, a, Wown & 0x10000u, rw.w2) ? 0x10000u : 0u;
-    fl |= cont_accept(up3, hf.w, twoJ, a, Wown & 0x1000000u, rw.w3) ? 0x1000000u : 0u;
-    return fl;
+    const float s0 = (float)(Wown & 0xFFu), s1 = (float)((Wown >> 8) & 0xFFu);
+    const float s2 = (float)((Wown >> 16) & 0xFFu), s3 = (float)(Wown >> 24);
+    const uint32_t b0 = cont_bound(up0, s0, hf.x, twoJ, a), b1 = cont_bound(up1, s1, hf.y, twoJ, a);
+    const uint32_t b2 = cont_bound(up2, s2, hf.z, twoJ, a), b3 = cont_bound(up3, s3, hf.w, twoJ, a);
+    const uint32_t acc = accept_bits(rw.w0, rw.w1, rw.w2, rw.w3, b0, b1, b2, b3);
+    return __umul24(acc, 0x204081u) & 0x01010101u;
 }
 
 // One chunk's half-sweep update; returns the new own words (and the loaded
