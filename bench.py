@@ -124,6 +124,71 @@ def copy_only(torch, nbytes, reps=5):
     log("copy mode: %d copies of %d bytes (read %d, write %d per copy)" % (reps, nbytes, nbytes, nbytes))
 
 
+def cpu_worker(q, sweeps=20):
+    """Child process of the all-cores figure: the oracle on realization q of
+    the L=64 workload (no GPU, no torch), one JSON line on stdout."""
+    from paper_1508_06268_amd import workloads as W
+    from oracle import oracle as O
+
+    w = W.adaptive_l64()
+    o = O.Oracle(w.L, w.R, w.J, w.h, W.bimodal_fields(w.L, [9, q]), w.temps, seed=w.seed, realization=q)
+    t0 = time.perf_counter()
+    o.sweep(sweeps, w.every)
+    dt = time.perf_counter() - t0
+    print(json.dumps({"attempts": w.R * w.L ** 3 * sweeps, "seconds": dt}), flush=True)
+
+
+def cpu_all_cores(procs):
+    """`procs` independent oracle processes on different realizations at
+    once (started as child processes of a fresh interpreter); aggregate
+    attempts over the wall time of the slowest."""
+    import subprocess
+
+    from oracle import oracle as O
+
+    O.build()
+    t0 = time.perf_counter()
+    ps = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", str(q)],
+                           stdout=subprocess.PIPE, cwd=ROOT) for q in range(procs)]
+    outs = [json.loads(p.communicate()[0].decode().strip().splitlines()[-1]) for p in ps]
+    wall = time.perf_counter() - t0
+    if any(p.returncode != 0 for p in ps):
+        raise RuntimeError("an oracle worker failed")
+    att = sum(o["attempts"] for o in outs)
+    return {"value": att / (wall * 1e9), "unit": "spin-flip attempts/ns", "cores": procs,
+            "sample": "%d processes x (L=64, R=128, 20 sweeps, exchange every 10), %.1f s wall" % (procs, wall)}
+
+
+def hbm_streaming_leg(torch, P, W, every=10, sweeps=200):
+    """The dominant kernel on data that does not fit the on-package cache:
+    16 realizations x R=128 at L=64 (512 MiB of spins) in one batch, so each
+    half-sweep launch covers 2048 replicas and streams them through HBM."""
+    specs = W.hbm_streaming_l64(sweeps=sweeps)
+    stream = torch.cuda.Stream()
+    b = P.Batch(specs, stream=stream)
+    b.sweep(every, every)                  # graph capture outside the timed region
+    b.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    b.sweep(sweeps, every)
+    e1.record(stream)
+    b.synchronize()
+    dt = e0.elapsed_time(e1) / 1e3
+    b.close()
+    attempts = sum(w.R * w.L ** 3 for w in specs) * sweeps
+    spins_bytes = sum(w.R * w.L ** 3 for w in specs)
+    rate = attempts / dt / 1e9
+    gbs = BYTES_PER_ATTEMPT[0] * attempts / dt / 1e9
+    log("hbm streaming: %d x L=64 R=%d (%.0f MiB of spins), %d sweeps: %.1f attempts/ns, %.0f GB/s "
+        "algorithmic (%.1f%% of HBM)" % (len(specs), specs[0].R, spins_bytes / 2 ** 20, sweeps, rate, gbs,
+                                          100 * gbs / HBM_PEAK_GBS))
+    return {"workload": "hbm_streaming_l64", "realizations": len(specs), "L": 64, "R": specs[0].R,
+            "spins_mib": round(spins_bytes / 2 ** 20, 1), "sweeps": sweeps, "exchange_every": every,
+            "attempts_per_ns": round(rate, 1), "hbm_gbs_algorithmic": round(gbs, 1),
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def batched_leg(torch, P, W, n=256, sweeps=5000, every=10):
     """Many realizations of uneven L and R in one batch (one launch per
     class and half-sweep or interval, graph-replayed intervals, autotuned
@@ -256,11 +321,14 @@ def main():
                          "of --copy-bytes (counter calibration)")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-realizations leg")
+    ap.add_argument("--cpu-worker", type=int, default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_worker is not None:
+        cpu_worker(args.cpu_worker)
+        return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs a realization on a single MI355X "
-              "(multi-GPU sharding is described in DESIGN.md, not built); use --gpus 1",
-              file=sys.stderr)
+        print("bench.py measures one GPU: a realization runs on a single MI355X and sharding "
+              "across GPUs is not built; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -365,12 +433,17 @@ def main():
 
     for hh in handles:
         hh.close()
+    streaming = hbm_streaming_leg(torch, P, W)
+    roofline["hbm_streaming"] = streaming
     batched = None if args.no_batched else batched_leg(torch, P, W)
 
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a bounded sample")
         cpu = cpu_baseline(w)
+        procs = max(1, min(16, os.cpu_count() or 1))
+        log("cpu baseline: %d oracle processes at once" % procs)
+        cpu["all_cores"] = cpu_all_cores(procs)
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "spin-flip attempts/ns", "n_gpus": 1,

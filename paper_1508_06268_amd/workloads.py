@@ -90,6 +90,16 @@ def adaptive_l64(sweeps: int = 20_000, trials: int = 4, trial_sweeps: int = 2000
                                   rate_threshold=0.2, max_insert_per_trial=16, R_cap=192))
 
 
+def hbm_streaming_l64(n: int = 16, R: int = 128, sweeps: int = 200) -> list:
+    """The L=64 kernel on more data than the 256 MB on-package cache holds:
+    n realizations of L=64 with R replicas each (n R L^3 bytes of spins,
+    512 MiB at the defaults), +-1 fields h=2.25, T linear in [1, 6], run as
+    one batch so every half-sweep streams all of them through HBM."""
+    return [Realization(L=64, R=R, J=1.0, h=2.25, fields=bimodal_fields(64, [8, q]),
+                        temps=linear_temps(R, 1.0, 6.0), seed=0, realization=q, sweeps=sweeps, every=10)
+            for q in range(n)]
+
+
 def batched_mix(n: int = 256, sweeps: int = 5000) -> list:
     """n independent realizations, L uniform over {8, 16, 32} with R = 16/32/64,
     even ids bimodal, odd ids Gaussian, h ~ U[1.0, 2.5], T geometric in [1, 6]."""
