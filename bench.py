@@ -316,9 +316,9 @@ def main():
                     help="served_stream: the continuous-batching serving run (its own JSON line)")
     ap.add_argument("--production-sweeps", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="bench", choices=["bench", "kernel", "copy"],
-                    help="kernel: only the dominant kernel (for counters); copy: a plain copy "
-                         "of --copy-bytes (counter calibration)")
+    ap.add_argument("--mode", default="bench", choices=["bench", "kernel", "streaming", "copy"],
+                    help="kernel: only the dominant kernel (for counters); streaming: only the "
+                         "HBM-streaming leg; copy: a plain copy of --copy-bytes (counter calibration)")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-realizations leg")
     ap.add_argument("--cpu-worker", type=int, default=None, help=argparse.SUPPRESS)
@@ -341,6 +341,9 @@ def main():
         return
     if args.mode == "copy":
         copy_only(torch, args.copy_bytes)
+        return
+    if args.mode == "streaming":
+        hbm_streaming_leg(torch, P, W, sweeps=20)
         return
     if args.workload == "served_stream":
         served = served_leg(torch, P, W)
