@@ -1023,6 +1023,12 @@ struct rfim_batch {
     uint64_t t = 0, k = 0;
     hipGraphExec_t graph = nullptr;
     int graph_every = 0;
+    // side streams for classes (and halves of large streaming classes) that
+    // run concurrently within an exchange interval; events fork them from
+    // and join them back into `stream`
+    std::vector<hipStream_t> aux;
+    std::vector<hipEvent_t> ev_join;
+    hipEvent_t ev_fork = nullptr;
 };
 
 namespace {
@@ -1040,6 +1046,9 @@ void batch_free(rfim_batch *b) {
         free_device(h);
         delete h;
     }
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    for (hipEvent_t e : b->ev_join) (void)hipEventDestroy(e);
+    for (hipStream_t q : b->aux) (void)hipStreamDestroy(q);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
@@ -1101,18 +1110,74 @@ rfim_dev::Launch class_launch(const rfim_batch *b, const rfim_batch::Class &c) {
     return ln;
 }
 
+// Classes never share items, and the workgroups of one streaming launch
+// are independent within a half-sweep, so an interval's launches form
+// independent lanes: one per class, two for a streaming class of at least
+// kSplitMinAttempts sites per half.  Lanes go round-robin (largest first)
+// to the batch stream and up to kMaxSideStreams side streams.
+constexpr int kMaxSideStreams = 3;
+
+struct Lane {
+    rfim_dev::Launch ln;
+    long long work;
+};
+
+int ensure_side_streams(rfim_batch *b, int n) {
+    if (!b->ev_fork) HIPCHK(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+    while ((int)b->aux.size() < n) {
+        hipStream_t q = nullptr;
+        hipEvent_t e = nullptr;
+        HIPCHK(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+        b->aux.push_back(q);
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        b->ev_join.push_back(e);
+    }
+    return RFIM_OK;
+}
+
 // m sweeps of every item; exch: energies (fused) and one exchange step.
 int batch_segment(rfim_batch *b, int m, bool exch) {
+    std::vector<Lane> lanes;
     for (const auto &c : b->classes) {
         const rfim_dev::Launch ln = class_launch(b, c);
-        if (c.mode == 1) {
-            HIPCHK(rfim_dev::launch_resident(ln, m, exch ? 1 : 0, b->stream));
+        const long long sites = (long long)ln.nblocks * (c.mode == 1 ? (long long)c.L * c.L * c.L / 2
+                                                                      : 4ll * c.nw * c.wg);
+        if (c.mode == 0 && ln.nblocks >= 16 && sites / 2 >= kSplitMinAttempts) {
+            rfim_dev::Launch la = ln, lb = ln;
+            la.nblocks = (ln.nblocks / 2) & ~7;
+            lb.map = ln.map + la.nblocks;
+            lb.nblocks = ln.nblocks - la.nblocks;
+            lanes.push_back({la, sites / 2});
+            lanes.push_back({lb, sites / 2});
         } else {
-            for (int q = 0; q < m; ++q) {
-                HIPCHK(rfim_dev::launch_stream_sweep(ln, 0, q, 0, b->stream));
-                HIPCHK(rfim_dev::launch_stream_sweep(ln, 1, q, exch && q == m - 1, b->stream));
-            }
+            lanes.push_back({ln, sites});
         }
+    }
+    std::stable_sort(lanes.begin(), lanes.end(), [](const Lane &x, const Lane &y) { return x.work > y.work; });
+    const int nside = std::min((int)lanes.size() - 1, kMaxSideStreams);
+    std::vector<hipStream_t> qs(1, b->stream);
+    if (nside > 0) {
+        int rc;
+        if ((rc = ensure_side_streams(b, nside))) return rc;
+        HIPCHK(hipEventRecord(b->ev_fork, b->stream));
+        for (int j = 0; j < nside; ++j) {
+            HIPCHK(hipStreamWaitEvent(b->aux[j], b->ev_fork, 0));
+            qs.push_back(b->aux[j]);
+        }
+    }
+    const int nq = (int)qs.size();
+    for (size_t i = 0; i < lanes.size(); ++i)
+        if (lanes[i].ln.mode == 1)
+            HIPCHK(rfim_dev::launch_resident(lanes[i].ln, m, exch ? 1 : 0, qs[i % nq]));
+    for (int q = 0; q < m; ++q)
+        for (size_t i = 0; i < lanes.size(); ++i)
+            if (lanes[i].ln.mode == 0) {
+                HIPCHK(rfim_dev::launch_stream_sweep(lanes[i].ln, 0, q, 0, qs[i % nq]));
+                HIPCHK(rfim_dev::launch_stream_sweep(lanes[i].ln, 1, q, exch && q == m - 1, qs[i % nq]));
+            }
+    for (int j = 0; j < nside; ++j) {
+        HIPCHK(hipEventRecord(b->ev_join[j], b->aux[j]));
+        HIPCHK(hipStreamWaitEvent(b->stream, b->ev_join[j], 0));
     }
     if (exch) {
         HIPCHK(rfim_dev::launch_exchange(b->d_lats, (int)b->items.size(), m, b->stream));
@@ -1128,6 +1193,9 @@ int batch_capture(rfim_batch *b, int every) {
         b->graph = nullptr;
     }
     hipGraph_t g = nullptr;
+    int rc0;
+    // side streams and events exist before the capture starts
+    if ((rc0 = ensure_side_streams(b, kMaxSideStreams))) return rc0;
     HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     int rc = batch_segment(b, every, true);
     hipError_t e = hipStreamEndCapture(b->stream, &g);
@@ -1459,6 +1527,9 @@ void rfim_pool_destroy(rfim_pool_t *p) {
         b->own_stream = p->core.own_stream;
         b->d_lats = p->core.d_lats;
         b->classes = p->core.classes;
+        b->aux = p->core.aux;
+        b->ev_join = p->core.ev_join;
+        b->ev_fork = p->core.ev_fork;
         for (rfim *h : p->slots)
             if (h) b->items.push_back(h);
         batch_free(b);

@@ -258,28 +258,46 @@ __device__ __forceinline__ Chunk chunk_geometry(uint32_t j0, uint32_t colour, ui
     return c;
 }
 
-// Up-neighbour counts (per byte) of the NW words of a chunk.
+// The other-colour words around a chunk: the chunk's own pair words W, the
+// one dword of the adjacent chunk the x-shift needs, and the y+-1, z+-1 rows.
+template <int NW> struct Around {
+    uint32_t W[NW], Wx, Wyp[NW], Wym[NW], Wzp[NW], Wzm[NW];
+};
+
 template <int NW, class P>
-__device__ __forceinline__ void neighbour_counts(P oth, uint32_t j0, const Chunk &c, uint32_t (&W)[NW],
-                                                 uint32_t (&U)[NW]) {
-    uint32_t Wyp[NW], Wym[NW], Wzp[NW], Wzm[NW];
-    load_words<NW>(oth, j0, W);
-    const uint32_t Wx = *(typename rebind_ptr<P, const uint32_t>::type)(oth + c.jxw);
-    load_words<NW>(oth, c.jyp, Wyp);
-    load_words<NW>(oth, c.jym, Wym);
-    load_words<NW>(oth, c.jzp, Wzp);
-    load_words<NW>(oth, c.jzm, Wzm);
+__device__ __forceinline__ void load_around(P oth, uint32_t j0, const Chunk &c, Around<NW> &a) {
+    load_words<NW>(oth, j0, a.W);
+    a.Wx = *(typename rebind_ptr<P, const uint32_t>::type)(oth + c.jxw);
+    load_words<NW>(oth, c.jyp, a.Wyp);
+    load_words<NW>(oth, c.jym, a.Wym);
+    load_words<NW>(oth, c.jzp, a.Wzp);
+    load_words<NW>(oth, c.jzm, a.Wzm);
+}
+
+// Up-neighbour counts (per byte) of the NW words of a chunk.
+template <int NW>
+__device__ __forceinline__ void neighbour_sums(const Chunk &c, const Around<NW> &a, uint32_t (&U)[NW]) {
     // p = 1: bytes of pairs m+1..m+4 (bytes 1-3 of W[w], byte 0 of the next
     // word); p = 0: bytes of pairs m-1..m+2 (byte 3 of the previous word,
     // bytes 0-2 of W[w]).  One byte permute of {other word, W[w]}.
     const uint32_t sel = c.p ? 0x04030201u : 0x02010007u;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
-        const uint32_t nxt = (w + 1 < NW) ? W[w + 1 < NW ? w + 1 : 0] : Wx;
-        const uint32_t prv = (w > 0) ? W[w > 0 ? w - 1 : 0] : Wx;
-        const uint32_t Xs = __builtin_amdgcn_perm(c.p ? nxt : prv, W[w], sel);
-        U[w] = W[w] + Xs + Wyp[w] + Wym[w] + Wzp[w] + Wzm[w];
+        const uint32_t nxt = (w + 1 < NW) ? a.W[w + 1 < NW ? w + 1 : 0] : a.Wx;
+        const uint32_t prv = (w > 0) ? a.W[w > 0 ? w - 1 : 0] : a.Wx;
+        const uint32_t Xs = __builtin_amdgcn_perm(c.p ? nxt : prv, a.W[w], sel);
+        U[w] = a.W[w] + Xs + a.Wyp[w] + a.Wym[w] + a.Wzp[w] + a.Wzm[w];
     }
+}
+
+template <int NW, class P>
+__device__ __forceinline__ void neighbour_counts(P oth, uint32_t j0, const Chunk &c, uint32_t (&W)[NW],
+                                                 uint32_t (&U)[NW]) {
+    Around<NW> a;
+    load_around<NW>(oth, j0, c, a);
+    neighbour_sums<NW>(c, a, U);
+#pragma unroll
+    for (int w = 0; w < NW; ++w) W[w] = a.W[w];
 }
 
 // Bit q set iff u_q <= t_q, for four sites.  The compares write four lane
@@ -381,10 +399,25 @@ __device__ __forceinline__ uint32_t chunk_update(const Lattice &lat, const uint3
                                                  uint32_t (&W)[NW], uint32_t (&U)[NW],
                                                  uint32_t (&Wnew)[NW], uint32_t (&F4)[NW]) {
     const Chunk c = chunk_geometry<NW>(j0, colour, (uint32_t)lat.L, (uint32_t)lat.log2L, (uint32_t)lat.half);
+    // Every load of the chunk is issued before any arithmetic (the scheduling
+    // barrier keeps the compiler from sinking one next to its use): with many
+    // realizations in a launch the fields and rows miss in L2, and a load
+    // issued per Philox block would expose the memory latency each time.
     uint32_t Wown[NW];
     load_words<NW>(own, j0, Wown);
-    neighbour_counts<NW>(oth, j0, c, W, U);
-    if (KIND == 0) load_words<NW>(fb_own, j0, F4);
+    Around<NW> a;
+    load_around<NW>(oth, j0, c, a);
+    f32x4 HF[NW];
+    if (KIND == 0) {
+        load_words<NW>(fb_own, j0, F4);
+    } else {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) HF[w] = *(typename rebind_ptr<PF, const f32x4>::type)(hf_own + j0 + 4u * w);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    neighbour_sums<NW>(c, a, U);
+#pragma unroll
+    for (int w = 0; w < NW; ++w) W[w] = a.W[w];
     const uint32_t c3 = (kTagSweep << 28) | lat.rho;
     uint32_t any = 0;
 #pragma unroll
@@ -394,8 +427,7 @@ __device__ __forceinline__ uint32_t chunk_update(const Lattice &lat, const uint3
         if (KIND == 0) {
             fl = bimodal_flips<NEV>(sthr, U[w], Wown[w], F4[w], rw, never);
         } else {
-            const f32x4 hf = *(typename rebind_ptr<PF, const f32x4>::type)(hf_own + j0 + 4u * w);
-            fl = continuous_flips(U[w], Wown[w], hf, 2.0f * lat.Jf, -2.0f * 1.44269504088896341f * beta, rw);
+            fl = continuous_flips(U[w], Wown[w], HF[w], 2.0f * lat.Jf, -2.0f * 1.44269504088896341f * beta, rw);
         }
         any |= fl;
         Wnew[w] = Wown[w] ^ fl;
