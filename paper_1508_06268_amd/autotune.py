@@ -69,8 +69,13 @@ def _kind_of(w) -> int:
     return FIELDS_BIMODAL if np.all((f == 1.0) | (f == -1.0)) else FIELDS_CONTINUOUS
 
 
+# Bumped whenever the kernels or the timing method change, so that shapes
+# cached by an older build are measured again.
+CACHE_VERSION = 2
+
+
 def class_key(L: int, kind: int, items) -> str:
-    return "L%d_k%d_R%d_n%d" % (L, kind, sum(int(w.R) for w in items), len(items))
+    return "v%d_L%d_k%d_R%d_n%d" % (CACHE_VERSION, L, kind, sum(int(w.R) for w in items), len(items))
 
 
 def load_cache(path: str = DEFAULT_CACHE) -> Dict[str, list]:
@@ -123,21 +128,24 @@ def tune(specs, every: int = 10, intervals: int = 3, cache_path: Optional[str] =
             todo.append(key)
     if todo:
         stream = torch.cuda.Stream()
-        probe = Batch(specs, stream=stream)
         for key in todo:
+            # each class is timed on its own (the classes of a batch run
+            # concurrently, so a whole-batch time would mix them), best of
+            # two passes over the candidates
             L, kind = key
-            timings = []
-            for shape in candidate_shapes(L):
-                probe.set_shape(L, kind, *shape)
-                ms = _time_batch(torch, probe, stream, every, intervals)
-                timings.append((ms, shape))
-                if log:
-                    log("tune L=%d kind=%d shape %s: %.3f ms" % (L, kind, shape, ms))
-            ms, shape = min(timings)
+            probe = Batch(classes[key], stream=stream)
+            timings = {}
+            for _ in range(2):
+                for shape in candidate_shapes(L):
+                    probe.set_shape(L, kind, *shape)
+                    ms = _time_batch(torch, probe, stream, every, intervals)
+                    timings[shape] = min(ms, timings.get(shape, ms))
+                    if log:
+                        log("tune L=%d kind=%d shape %s: %.3f ms" % (L, kind, shape, ms))
+            probe.close()
+            shape = min(timings, key=lambda sh: (timings[sh], sh))
             best[key] = shape
-            probe.set_shape(L, kind, *shape)
             cache[class_key(L, kind, classes[key])] = list(shape)
-        probe.close()
         if cache_path:
             save_cache(cache, cache_path)
     return best
