@@ -66,6 +66,8 @@ def lib():
         L.orc_exchange_stats.argtypes = [vp, vp, vp]
         L.orc_flip_delta.argtypes = [vp, i32, i32]
         L.orc_flip_delta.restype = dbl
+        L.orc_accept.argtypes = [vp, i32, i32, u32]
+        L.orc_accept.restype = i32
         L.orc_thresholds.argtypes = [vp, vp, vp]
         L.orc_adapt_temps.argtypes = [vp, i32, i64, i32, dbl, i32, i32]
         L.orc_adapt_temps.restype = i32
@@ -193,6 +195,10 @@ class Oracle:
 
     def flip_delta(self, r, i) -> float:
         return lib().orc_flip_delta(self._h, int(r), int(i))
+
+    def accept(self, r, i, u) -> bool:
+        """The sweep's decision for site i of replica r with word u."""
+        return bool(self._check(lib().orc_accept(self._h, int(r), int(i), int(u) & 0xFFFFFFFF)))
 
     def thresholds(self):
         thr = np.zeros((self.R, 14), dtype=np.uint32)

@@ -344,6 +344,11 @@ static int accept_flip(const orc_t *o, const int8_t *s, int i, int slot, uint32_
     return (double)u < ldexp(p, 32);
 }
 
+int orc_accept(const orc_t *o, int r, int i, uint32_t u) {
+    if (r < 0 || r >= o->R || i < 0 || i >= o->N) return -1;
+    return accept_flip(o, o->s + (size_t)r * o->N, i, o->r2t[r], u);
+}
+
 static void half_sweep(orc_t *o, int c) {
     int half = o->N / 2;
     for (int r = 0; r < o->R; ++r) {

@@ -77,6 +77,10 @@ int orc_exchange_once(orc_t *o);
 /* Energy change the sweep would use for flipping site i of replica r. */
 double orc_flip_delta(const orc_t *o, int r, int i);
 
+/* The sweep's own decision for site i of replica r (at its current slot)
+ * with random word u: 1 flip, 0 keep, -1 bad arguments. */
+int orc_accept(const orc_t *o, int r, int i, uint32_t u);
+
 /* Acceptance thresholds the sweep uses for bimodal fields: thr[R][14],
  * always[14] (1 where Delta E <= 0).  Class index = 2*k + fb with k the
  * number of the six neighbour slots aligned with s_i and fb = 1 iff
