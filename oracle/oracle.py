@@ -68,6 +68,8 @@ def lib():
         L.orc_flip_delta.restype = dbl
         L.orc_accept.argtypes = [vp, i32, i32, u32]
         L.orc_accept.restype = i32
+        L.orc_fourier.argtypes = [vp, vp]
+        L.orc_fourier.restype = i32
         L.orc_thresholds.argtypes = [vp, vp, vp]
         L.orc_adapt_temps.argtypes = [vp, i32, i64, i32, dbl, i32, i32]
         L.orc_adapt_temps.restype = i32
@@ -195,6 +197,12 @@ class Oracle:
 
     def flip_delta(self, r, i) -> float:
         return lib().orc_flip_delta(self._h, int(r), int(i))
+
+    def fourier(self) -> np.ndarray:
+        """F of the correlation length for the configuration at every slot."""
+        F = np.zeros(self.R, dtype=np.float64)
+        self._check(lib().orc_fourier(self._h, _p(F)))
+        return F
 
     def accept(self, r, i, u) -> bool:
         """The sweep's decision for site i of replica r with word u."""

@@ -20,6 +20,7 @@
  *     replica->slot permutations (Sec. 3.3, "trs"/"rts").
  *   - Adaptive insertion of temperatures at the midpoint of the
  *     lowest-exchange-rate intervals after short trial runs (Sec. 4).
+ *   - The Fourier observable of the correlation length (Sec. 7).
  *
  * Conventions the paper leaves open (random number generator, colour order,
  * counter mapping, acceptance precision) are fixed here and written out in
@@ -80,6 +81,10 @@ double orc_flip_delta(const orc_t *o, int r, int i);
 /* The sweep's own decision for site i of replica r (at its current slot)
  * with random word u: 1 flip, 0 keep, -1 bad arguments. */
 int orc_accept(const orc_t *o, int r, int i, uint32_t u);
+
+/* Fourier observable of the correlation length (Sec. 7) of the current
+ * configuration at every slot: F[R], see rfim_oracle.c. */
+int orc_fourier(const orc_t *o, double *F);
 
 /* Acceptance thresholds the sweep uses for bimodal fields: thr[R][14],
  * always[14] (1 where Delta E <= 0).  Class index = 2*k + fb with k the
