@@ -170,6 +170,22 @@ int rfim_reset_exchange_stats(rfim_t *h);
 int rfim_observables(rfim_t *h, double *obs);
 int rfim_reset_observables(rfim_t *h);
 
+/* Optional measurement for the correlation length (Sec. 7): with
+ * RFIM_MEASURE_FOURIER set, every exchange step also adds, per slot,
+ *   F = (1/(3N)) sum_mu [(sum_i s_i cos(K x_mu,i))^2 + (sum_i s_i sin(K x_mu,i))^2]
+ * of the configuration now at that slot (K = 2 pi / L, mu over the three
+ * axes; the printed formula's field h_i read as the spin s_i).  Costs two
+ * small launches per exchange step and reads every spin once.  flags = 0
+ * turns it off.  The first call with the flag allocates R_cap * L * 2L * 4
+ * + (2L + 2 R_cap) * 8 bytes of device memory (RFIM_ENOMEM if that fails).
+ * Works for standalone handles and for batch and pool items (their
+ * batch's exchange steps measure them).  RFIM_EINVAL for unknown flags. */
+#define RFIM_MEASURE_FOURIER 1
+int rfim_set_measure(rfim_t *h, int flags);
+/* fourier = host [R][2]: per slot, the number of samples and the sum of F
+ * (FP64).  Reset with the other observables.  Synchronizes. */
+int rfim_fourier(rfim_t *h, double *fourier);
+
 /* Launch shape of the sweep kernels (no effect on results: every shape
  * gives bit-identical chains).  For L = 2^l >= 8: mode 0 streams every
  * half-sweep through HBM with nw in {1, 2, 4, 8} dwords (4 sites each, at

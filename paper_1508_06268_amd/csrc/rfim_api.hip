@@ -62,6 +62,10 @@ struct rfim {
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int concurrency = 0;            // see rfim_set_concurrency
+    // optional Fourier measurement (rfim_set_measure)
+    int measure = 0;
+    int32_t *d_fpart = nullptr;
+    double *d_trig = nullptr, *d_fobs = nullptr;
     // device memory
     uint8_t *d_spins = nullptr, *d_fbits = nullptr;
     float *d_fhf = nullptr, *d_fraw = nullptr, *d_betaf = nullptr;
@@ -131,6 +135,9 @@ void free_device(rfim *h) {
     if (h->d_lat) (void)hipFree(h->d_lat);
     if (h->d_smap) (void)hipFree(h->d_smap);
     if (h->d_rmap) (void)hipFree(h->d_rmap);
+    if (h->d_fpart) (void)hipFree(h->d_fpart);
+    if (h->d_trig) (void)hipFree(h->d_trig);
+    if (h->d_fobs) (void)hipFree(h->d_fobs);
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);
     if (h->aux) (void)hipStreamDestroy(h->aux);
@@ -364,6 +371,14 @@ int reset_stats(rfim *h) {
 
 int reset_obs(rfim *h) {
     HIPCHK(hipMemsetAsync(h->d_obs, 0, (size_t)h->R_cap * 6 * sizeof(double), h->stream));
+    if (h->d_fobs) HIPCHK(hipMemsetAsync(h->d_fobs, 0, (size_t)h->R_cap * 2 * sizeof(double), h->stream));
+    return RFIM_OK;
+}
+
+// After an exchange step: the Fourier sample of every replica, by slot.
+int measure_after_exchange(rfim *h, hipStream_t s) {
+    if (!(h->measure & RFIM_MEASURE_FOURIER)) return RFIM_OK;
+    HIPCHK(rfim_dev::launch_fourier(h->lattice(), h->d_fpart, h->d_trig, h->d_fobs, s));
     return RFIM_OK;
 }
 
@@ -537,6 +552,8 @@ int sweep_impl(rfim *h, int64_t n, int every) {
         if (exch) {
             if (!fused) HIPCHK(rfim_dev::launch_energy(lat, h->stream));
             HIPCHK(rfim_dev::launch_exchange(h->d_lat, 1, m, h->stream));
+            int rc;
+            if ((rc = measure_after_exchange(h, h->stream))) return rc;
             h->k += 1;
         } else {
             HIPCHK(rfim_dev::launch_advance(lat, m, h->stream));
@@ -864,6 +881,51 @@ int rfim_get_launch_shape(const rfim_t *h, int *mode, int *nw, int *wg) {
     return RFIM_OK;
 }
 
+int rfim_set_measure(rfim_t *h, int flags) {
+    if (!h) return fail(RFIM_EINVAL, "handle is NULL");
+    if (flags & ~RFIM_MEASURE_FOURIER) return fail(RFIM_EINVAL, "unknown measurement flags %d", flags);
+    if ((flags & RFIM_MEASURE_FOURIER) && !h->d_fpart) {
+        const size_t L = (size_t)h->L, Rc = (size_t)h->R_cap;
+        if (hipMalloc((void **)&h->d_fpart, Rc * L * 2 * L * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc((void **)&h->d_trig, 2 * L * sizeof(double)) != hipSuccess ||
+            hipMalloc((void **)&h->d_fobs, Rc * 2 * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            if (h->d_fpart) (void)hipFree(h->d_fpart);
+            if (h->d_trig) (void)hipFree(h->d_trig);
+            if (h->d_fobs) (void)hipFree(h->d_fobs);
+            h->d_fpart = nullptr;
+            h->d_trig = nullptr;
+            h->d_fobs = nullptr;
+            return fail(RFIM_ENOMEM, "no device memory for the Fourier measurement");
+        }
+        // cos and sin of 2 pi v / L with the host libm (the same values the
+        // reference computation uses)
+        std::vector<double> trig(2 * L);
+        for (size_t v = 0; v < L; ++v) {
+            trig[v] = std::cos(2.0 * 3.14159265358979323846 * (double)v / (double)L);
+            trig[L + v] = std::sin(2.0 * 3.14159265358979323846 * (double)v / (double)L);
+        }
+        HIPCHK(hipMemcpyAsync(h->d_trig, trig.data(), trig.size() * sizeof(double), hipMemcpyHostToDevice,
+                              h->stream));
+        HIPCHK(hipMemsetAsync(h->d_fobs, 0, Rc * 2 * sizeof(double), h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    h->measure = flags;
+    return RFIM_OK;
+}
+
+int rfim_fourier(rfim_t *h, double *fourier) {
+    if (!h || !fourier) return fail(RFIM_EINVAL, "NULL argument");
+    if (!h->d_fobs) {
+        std::memset(fourier, 0, (size_t)h->R * 2 * sizeof(double));
+        return RFIM_OK;
+    }
+    HIPCHK(hipMemcpyAsync(fourier, h->d_fobs, (size_t)h->R * 2 * sizeof(double), hipMemcpyDeviceToHost,
+                          h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return RFIM_OK;
+}
+
 int rfim_set_concurrency(rfim_t *h, int streams) {
     if (!h) return fail(RFIM_EINVAL, "handle is NULL");
     if (streams < 0 || streams > 2) return fail(RFIM_EINVAL, "streams must be 0, 1 or 2 (got %d)", streams);
@@ -1023,6 +1085,7 @@ struct rfim_batch {
     uint64_t t = 0, k = 0;
     hipGraphExec_t graph = nullptr;
     int graph_every = 0;
+    std::vector<int> graph_measure;     // items' measurement flags the graph was captured with
     // side streams for classes (and halves of large streaming classes) that
     // run concurrently within an exchange interval; events fork them from
     // and join them back into `stream`
@@ -1181,6 +1244,10 @@ int batch_segment(rfim_batch *b, int m, bool exch) {
     }
     if (exch) {
         HIPCHK(rfim_dev::launch_exchange(b->d_lats, (int)b->items.size(), m, b->stream));
+        for (rfim *h : b->items) {
+            int rc;
+            if ((rc = measure_after_exchange(h, b->stream))) return rc;
+        }
     } else {
         for (rfim *h : b->items) HIPCHK(rfim_dev::launch_advance(h->lattice(), m, b->stream));
     }
@@ -1356,7 +1423,12 @@ int rfim_batch_sweep(rfim_batch_t *b, int64_t n, int exchange_every) {
         const bool exch = every > 0 && m == to_next;
         int rc;
         if (exch && m == every) {
-            if (b->graph_every != every && (rc = batch_capture(b, every))) return rc;
+            std::vector<int> flags(b->items.size());
+            for (size_t q = 0; q < b->items.size(); ++q) flags[q] = b->items[q]->measure;
+            if (b->graph_every != every || b->graph_measure != flags) {
+                if ((rc = batch_capture(b, every))) return rc;
+                b->graph_measure = flags;
+            }
             HIPCHK(hipGraphLaunch(b->graph, b->stream));
         } else if ((rc = batch_segment(b, m, exch))) {
             return rc;

@@ -105,5 +105,9 @@ hipError_t launch_reduce(const Lattice &lat, int64_t *B, double *F, int64_t *M, 
 // One exchange step for each of the n realizations in lats (device array).
 hipError_t launch_exchange(const Lattice *lats, int n, int tadv, hipStream_t s);
 hipError_t launch_advance(const Lattice &lat, int tadv, hipStream_t s);
+// Fourier observable of every replica, accumulated by slot (rfim_measure.hip):
+// part int32 [R_cap][L][2L] scratch, trig double [2][L] = cos, sin of
+// 2 pi v / L, fobs double [R_cap][2] = (count, sum F).
+hipError_t launch_fourier(const Lattice &lat, int32_t *part, const double *trig, double *fobs, hipStream_t s);
 
 }  // namespace rfim_dev

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_PKG, "librfim.so")
 
 RFIM_OK, RFIM_EINVAL, RFIM_ENOMEM, RFIM_EDEVICE, RFIM_ESTATE, RFIM_ECAP, RFIM_EBUSY = 0, -1, -2, -3, -4, -5, -6
 FIELDS_AUTO, FIELDS_BIMODAL, FIELDS_CONTINUOUS = -1, 0, 1
+MEASURE_FOURIER = 1
 
 # Every symbol include/rfim.h declares (checked by the CPU tests).
 EXPORTS = [
@@ -28,7 +29,7 @@ EXPORTS = [
     "rfim_get_perm", "rfim_set_perm", "rfim_get_counters", "rfim_set_counters",
     "rfim_exchange_stats", "rfim_reset_exchange_stats", "rfim_save", "rfim_load",
     "rfim_set_launch_shape", "rfim_get_launch_shape", "rfim_set_concurrency", "rfim_get_concurrency",
-    "rfim_observables", "rfim_reset_observables",
+    "rfim_observables", "rfim_reset_observables", "rfim_set_measure", "rfim_fourier",
     "rfim_batch_create", "rfim_batch_destroy", "rfim_batch_size", "rfim_batch_sweep",
     "rfim_batch_synchronize", "rfim_batch_item", "rfim_batch_set_shape",
     "rfim_pool_create", "rfim_pool_destroy", "rfim_pool_bytes_needed", "rfim_pool_admit",
@@ -95,6 +96,8 @@ def load_library(path: str = LIB_PATH):
         "rfim_set_launch_shape": (i32, [vp, i32, i32, i32]),
         "rfim_get_launch_shape": (i32, [vp, vp, vp, vp]),
         "rfim_set_concurrency": (i32, [vp, i32]),
+        "rfim_set_measure": (i32, [vp, i32]),
+        "rfim_fourier": (i32, [vp, vp]),
         "rfim_get_concurrency": (i32, [vp]),
         "rfim_observables": (i32, [vp, vp]),
         "rfim_reset_observables": (i32, [vp]),
@@ -313,6 +316,17 @@ class Rfim:
 
     def reset_observables(self):
         _check(load_library().rfim_reset_observables(self._h))
+
+    def set_measure(self, flags: int):
+        """MEASURE_FOURIER: also sample the correlation-length observable F
+        at every exchange step (see rfim_set_measure)."""
+        _check(load_library().rfim_set_measure(self._h, int(flags)))
+
+    def fourier(self) -> np.ndarray:
+        """Per slot: [count, sum F]."""
+        o = np.zeros((self.R, 2), dtype=np.float64)
+        _check(load_library().rfim_fourier(self._h, _p(o)))
+        return o
 
     def launch_shape(self):
         m, nw, wg = C.c_int(), C.c_int(), C.c_int()

@@ -249,3 +249,32 @@ def test_forced_split_small_lattice(rfim_mod, oracle_mod):
     with pytest.raises(rfim_mod.RfimError):
         g.set_concurrency(3)
     g.close()
+
+
+@pytest.mark.parametrize("L,R,shape", [(8, 5, None), (16, 4, (0, 2, 128)), (6, 3, None)])
+def test_fourier_measurement_matches_oracle_replay(rfim_mod, oracle_mod, L, R, shape):
+    """The correlation-length samples the device adds after every exchange
+    step equal the oracle's F of the configuration at each slot, replayed
+    step by step: integer plane sums make the FP64 arithmetic identical, so
+    the sums agree bit for bit.  Resident, streaming and generic kernels."""
+    f = W.bimodal_fields(L, [44, L])
+    T = W.linear_temps(R, 2.0, 6.0)
+    g, o = make_pair(rfim_mod, oracle_mod, L, R, 1.0, 1.0, f, T, seed=12)
+    if shape is not None:
+        g.set_launch_shape(*shape)
+    g.set_measure(rfim_mod.MEASURE_FOURIER)
+    g.sweep(60, 10)
+    want = np.zeros((R, 2))
+    for _ in range(6):
+        o.sweep(10, 10)
+        want[:, 0] += 1.0
+        want[:, 1] += o.fourier()
+    assert np.array_equal(g.fourier(), want)
+    g.reset_observables()
+    assert not g.fourier().any()
+    g.set_measure(0)
+    g.sweep(10, 10)
+    assert not g.fourier().any()
+    with pytest.raises(rfim_mod.RfimError):
+        g.set_measure(2)
+    g.close()

@@ -40,3 +40,24 @@ def test_crossing():
     T = np.array([1.0, 2.0, 3.0, 4.0])
     assert ob.crossing(T, [4, 3, 2, 1], [1, 2, 3, 4]) == pytest.approx(2.5)
     assert ob.crossing(T, [1, 1, 1, 1], [0, 0, 0, 0]) is None
+
+
+def test_correlation_length_of_an_ornstein_zernike_form():
+    """With chi(k) = chi0 / (1 + xi^2 4 sin^2(k/2)), <M^2>/N = chi0 and
+    <F> = chi(2 pi / L) give back xi; xi_paper lacks the 2 sin(pi/L)."""
+    L = 16
+    N = L ** 3
+    xi = np.array([0.5, 2.0, 5.0])
+    chi0 = np.array([3.0, 40.0, 400.0])
+    F = chi0 / (1.0 + xi ** 2 * 4 * np.sin(np.pi / L) ** 2)
+    n = 1000.0
+    obs = np.zeros((3, 6))
+    obs[:, 0] = n
+    obs[:, 4] = n * chi0 * N          # sum of M^2
+    obs[:, 5] = n * (chi0 * N) ** 2   # any positive M^4
+    fo = np.stack([np.full(3, n), n * F], axis=1)
+    th = ob.thermal(obs, np.array([1.0, 2.0, 3.0]), N, fourier=fo)
+    assert np.allclose(th["xi"], xi)
+    assert np.allclose(th["xi_paper"], xi * 2 * np.sin(np.pi / L))
+    avg = ob.disorder_average([th, th])
+    assert np.allclose(avg["xi"], xi)
