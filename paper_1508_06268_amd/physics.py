@@ -15,16 +15,19 @@ import numpy as np
 
 from . import observables as ob
 from . import workloads as W
-from .rfim import Batch
+from .rfim import MEASURE_FOURIER, Batch
 
 
-def binder_study(Ls: Sequence[int], realizations: int, temps: np.ndarray, h: float = 1.0,
+def binder_study(Ls: Sequence[int], realizations, temps: np.ndarray, h: float = 1.0,
                  J: float = 1.0, equilibration: int = 2000, measure: int = 4000, every: int = 10,
-                 seed: int = 0, stream=None) -> Dict[int, Dict[str, np.ndarray]]:
-    """[<|m|>], [C], [g] per size for +-1 fields of strength h."""
+                 seed: int = 0, stream=None, correlation: bool = False) -> Dict[int, Dict[str, np.ndarray]]:
+    """[<|m|>], [C], [g] per size for +-1 fields of strength h (and [xi],
+    [xi_paper] with `correlation`).  `realizations` is one count for every
+    size or a dict size -> count."""
+    counts = realizations if isinstance(realizations, dict) else {L: realizations for L in Ls}
     specs = []
     for L in Ls:
-        for q in range(realizations):
+        for q in range(counts[L]):
             specs.append(W.Realization(L=L, R=len(temps), J=J, h=h, fields=W.bimodal_fields(L, [7, L, q]),
                                        temps=np.asarray(temps, dtype=np.float64), seed=seed,
                                        realization=(L << 16) | q, sweeps=equilibration + measure,
@@ -34,15 +37,18 @@ def binder_study(Ls: Sequence[int], realizations: int, temps: np.ndarray, h: flo
     b.synchronize()
     for q in range(len(specs)):
         b.item(q).reset_observables()
+        if correlation:
+            b.item(q).set_measure(MEASURE_FOURIER)
     b.sweep(measure, every)
     b.synchronize()
     out = {}
     q = 0
     for L in Ls:
         per = []
-        for _ in range(realizations):
+        for _ in range(counts[L]):
             it = b.item(q)
-            per.append(ob.thermal(it.observables(), it.temps(), L ** 3))
+            per.append(ob.thermal(it.observables(), it.temps(), L ** 3,
+                                  fourier=it.fourier() if correlation else None))
             q += 1
         out[L] = ob.disorder_average(per)
     b.close()
