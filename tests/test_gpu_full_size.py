@@ -97,3 +97,30 @@ def test_batched_mix_full_size_sampled(rfim_mod):
         assert it.counters() == g.counters() == (5000, 500)
         g.close()
     b.close()
+
+
+@pytest.mark.parametrize("L,R,sweeps,every,shape", [
+    (128, 3, 3, 1, (0, 8, 256)),    # fused energy partials, eight-dword rows, two exchange steps
+    (256, 2, 2, 1, (0, 4, 128)),    # more workgroups per replica than the fused energy path takes
+    (512, 1, 1, 1, (0, 4, 256)),    # 2^27 sites: 32-bit offsets near their use, one replica
+])
+def test_large_lattices_match_oracle(rfim_mod, oracle_mod, L, R, sweeps, every, shape):
+    """Large lattices, up to 2^27 sites per replica: the same chain as the
+    oracle bit for bit (spins, permutation, energies) and the same Fourier
+    samples, through the energy path that does not fuse into the sweep."""
+    f = W.bimodal_fields(L, [45, L])
+    T = W.linear_temps(R, 2.0, 5.0) if R > 1 else np.array([3.0])
+    g = rfim_mod.Rfim(L, R, 1.0, 1.0, f, T, seed=46)
+    g.set_launch_shape(*shape)
+    g.set_measure(rfim_mod.MEASURE_FOURIER)
+    o = oracle_mod.Oracle(L, R, 1.0, 1.0, f, T, seed=46)
+    want_f = np.zeros((R, 2))
+    for _ in range(sweeps // every):
+        o.sweep(every, every)
+        want_f[:, 0] += 1.0
+        want_f[:, 1] += o.fourier()
+    g.sweep(sweeps, every)
+    assert_same_state(g, o, "L=%d" % L)
+    assert np.array_equal(g.fourier(), want_f)
+    g.close()
+    o.close()
