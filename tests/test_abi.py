@@ -65,4 +65,6 @@ def test_null_handle_getters_and_setters_fail_cleanly(rfim_mod):
     assert lib.rfim_get_concurrency(None) == -1
     assert lib.rfim_set_launch_shape(None, 0, 4, 128) == -1
     assert lib.rfim_num_replicas(None) == -1
+    assert lib.rfim_set_measure(None, 1) == -1
+    assert lib.rfim_fourier(None, None) == -1
     assert b"NULL" in lib.rfim_last_error()
