@@ -112,6 +112,7 @@ struct rfim {
         a.acc = d_acc;
         a.ctrs = d_ctrs;
         a.part = d_part;
+        a.pstride = R_cap;
         a.nblk = nblk;
         a.mode = mode;
         a.nw = nw;

@@ -26,7 +26,10 @@ namespace rfim_dev {
 //   beta   double [R_cap]         per slot (exchange).
 //   t2r, r2t int32 [R_cap]; att, acc uint64 [R_cap]
 //   ctrs   uint64 [2]             global sweep counter t, exchange counter k.
-//   part   double [R_cap][nblk][3] energy partials (B, F, M) per block;
+//   part   double [nblk][R_cap][3] energy partials (B, F, M) per block,
+//                                 block-major so that consecutive replicas'
+//                                 partials of one block are adjacent (the
+//                                 reduction reads them coalesced);
 //                                 nblk = blocks_per_replica(shape).
 //   E      double [R_cap]         energy by replica id after a reduction.
 //   Mr     double [R_cap]         magnetisation by replica id (same reduction).
@@ -51,6 +54,7 @@ struct Lattice {
     uint64_t *ctrs;
     double *part;
     int nblk;                   // energy partials per replica
+    int pstride;                // replicas per block row of part (R_cap)
     int mode;                   // power-of-two L: 0 streaming, 1 LDS-resident
     int nw, wg;                 // dwords per thread, threads per workgroup
     double *E;

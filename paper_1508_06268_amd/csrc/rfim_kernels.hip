@@ -220,12 +220,6 @@ __device__ __forceinline__ void store_words(P base, uint32_t off, const uint32_t
     }
 }
 
-__device__ __forceinline__ int wave_isum(int v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -491,10 +485,11 @@ __device__ __forceinline__ void block_partial(PD dst, int nsite, int ksum, int u
     __shared__ double red[3][16];
     const int bpart = 2 * ksum - 6 * nsite;
     const int mpart = 2 * upsum - 2 * nsite;
-    if (KIND == 0) fsum = (double)(2 * eqsum - 2 * nsite);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int vb = wave_isum(bpart), vm = wave_isum(mpart);
-    const double vf = wave_sum(fsum);
+    // integer sums over the wave's active lanes (DPP reduction in the
+    // device library; exact, so the order does not matter)
+    const int vb = __ockl_wfred_add_i32(bpart), vm = __ockl_wfred_add_i32(mpart);
+    const double vf = KIND == 0 ? (double)__ockl_wfred_add_i32(2 * eqsum - 2 * nsite) : wave_sum(fsum);
     if (lane == 0) {
         red[0][wave] = (double)vb;
         red[1][wave] = vf;
@@ -563,7 +558,7 @@ __global__ __launch_bounds__(256) void sweep_pow2(Lattice lat0, const Lattice *_
         double fsum = 0.0;
         chunk_energy<KIND, NW>(lat, Wnew, W, U, F4, fbits, fraw + lat.half, fraw, j0, ksum, upsum, eqsum,
                                fsum);
-        block_partial<KIND>(gptr(lat.part) + ((size_t)r * lat.nblk + gb) * 3, 4 * NW, ksum, upsum, eqsum,
+        block_partial<KIND>(gptr(lat.part) + ((size_t)gb * lat.pstride + r) * 3, 4 * NW, ksum, upsum, eqsum,
                             fsum);
     }
 }
@@ -628,7 +623,7 @@ __global__ __launch_bounds__(1024) void sweep_resident(Lattice lat0, const Latti
         // every thread covered 4*NW sites per chunk it took; nsite per thread
         // differs, so fold the affine offsets into the total instead
         const int nch = (int)((nchunk > threadIdx.x) ? (nchunk - 1 - threadIdx.x) / blockDim.x + 1 : 0);
-        block_partial<KIND>(gptr(lat.part) + (size_t)r * lat.nblk * 3, 4 * NW * nch, ksum, upsum, eqsum, fsum);
+        block_partial<KIND>(gptr(lat.part) + (size_t)r * 3, 4 * NW * nch, ksum, upsum, eqsum, fsum);
     }
     GAS u32x4 *dst = (GAS u32x4 *)(gptr(lat.spins) + (size_t)r * N);
     for (uint32_t q = threadIdx.x; q < N / 16u; q += blockDim.x) dst[q] = lds4[q];
@@ -684,7 +679,7 @@ __global__ __launch_bounds__(256) void energy_kernel(Lattice lat) {
     if (threadIdx.x < 3) {
         const double v = ((red[threadIdx.x][0] + red[threadIdx.x][1]) + red[threadIdx.x][2]) +
                          red[threadIdx.x][3];
-        lat.part[((size_t)r * lat.nblk + blockIdx.x) * 3 + threadIdx.x] = v;
+        lat.part[((size_t)blockIdx.x * lat.pstride + r) * 3 + threadIdx.x] = v;
     }
 }
 
@@ -692,49 +687,74 @@ __device__ __forceinline__ double energy_of(const Lattice &lat, double B, double
     return -(lat.J * B) - (lat.h * F);
 }
 
-// Partials of replica r summed in block order (one lane per replica; the
-// same order everywhere, so FP64 totals are reproducible).
-__device__ __forceinline__ void replica_totals(const Lattice &lat, int r, double &B, double &F, double &M) {
-    const double *pp = lat.part + (size_t)r * lat.nblk * 3;
-    B = 0.0;
-    F = 0.0;
-    M = 0.0;
-#pragma unroll 8
-    for (int b = 0; b < lat.nblk; ++b) {
-        B += pp[3 * b + 0];
-        F += pp[3 * b + 1];
-        M += pp[3 * b + 2];
-    }
-}
-
-// Totals per replica id; optional outputs for the observables calls.
-__global__ __launch_bounds__(256) void reduce_kernel(Lattice lat, int64_t *Bout, double *Fout,
-                                                     int64_t *Mout) {
-    for (int r = threadIdx.x; r < lat.R; r += 256) {
-        double B, F, M;
-        replica_totals(lat, r, B, F, M);
-        lat.E[r] = energy_of(lat, B, F);
-        if (Bout) Bout[r] = (int64_t)B;
-        if (Fout) Fout[r] = F;
-        if (Mout) Mout[r] = (int64_t)M;
-    }
-}
-
 // ---------------------------------------------------------------------
 // Exchange step k (Eq. 2): pairs (p, p+1) with p = k mod 2; temperatures
-// move through t2r / r2t (Sec. 3.3).  One workgroup.
+// move through t2r / r2t (Sec. 3.3).  One workgroup of kExchangeThreads.
 // ---------------------------------------------------------------------
-__global__ __launch_bounds__(256) void exchange_kernel(const Lattice *__restrict__ lats, int tadv) {
-    const Lattice &lat = lats[blockIdx.x];
-    for (int r = threadIdx.x; r < lat.R; r += 256) {
-        double B, F, M;
-        replica_totals(lat, r, B, F, M);
-        lat.E[r] = energy_of(lat, B, F);
-        lat.Mr[r] = M;
+constexpr int kExchangeThreads = 1024;
+
+// Energy and magnetisation of every replica from its partials (B, F, M per
+// block, block-major).  Thread (g, r) sums blocks [g per, (g+1) per) of
+// replica r in order -- consecutive threads take consecutive replicas, so
+// every load is coalesced, and all of a thread's loads are independent --
+// then one thread per replica adds its G range sums in order.  The order is
+// fixed for a given launch shape and replica count, so FP64 totals are
+// reproducible.  Writes E and Mr, and B, F, M when asked (observables).
+__device__ __forceinline__ void replica_totals(const Lattice &lat, int64_t *Bout = nullptr,
+                                               double *Fout = nullptr, int64_t *Mout = nullptr) {
+    __shared__ double red[kExchangeThreads * 3];
+    const int R = lat.R, nblk = lat.nblk;
+    int G = 1;
+    while (2 * G <= nblk && 2 * G <= 64 && (long long)R * 2 * G <= kExchangeThreads) G *= 2;
+    const int tile = kExchangeThreads / G, per = nblk / G;   // nblk and G are powers of two
+    const int g = (int)threadIdx.x / tile, rl = (int)threadIdx.x % tile;
+    for (int r0 = 0; r0 < R; r0 += tile) {
+        const int r = r0 + rl;
+        double b = 0.0, f = 0.0, m = 0.0;
+        if (r < R) {
+            const double *pp = lat.part + ((size_t)g * per * lat.pstride + r) * 3;
+            for (int q = 0; q < per; ++q) {
+                b += pp[(size_t)q * lat.pstride * 3 + 0];
+                f += pp[(size_t)q * lat.pstride * 3 + 1];
+                m += pp[(size_t)q * lat.pstride * 3 + 2];
+            }
+        }
+        red[3 * threadIdx.x + 0] = b;
+        red[3 * threadIdx.x + 1] = f;
+        red[3 * threadIdx.x + 2] = m;
+        __syncthreads();
+        if ((int)threadIdx.x < tile && r0 + (int)threadIdx.x < R) {
+            double B = red[3 * threadIdx.x + 0], F = red[3 * threadIdx.x + 1], M = red[3 * threadIdx.x + 2];
+            for (int q = 1; q < G; ++q) {
+                const double *rr = red + 3 * (q * tile + threadIdx.x);
+                B += rr[0];
+                F += rr[1];
+                M += rr[2];
+            }
+            const int rt = r0 + (int)threadIdx.x;
+            lat.E[rt] = energy_of(lat, B, F);
+            lat.Mr[rt] = M;
+            if (Bout) Bout[rt] = (int64_t)B;
+            if (Fout) Fout[rt] = F;
+            if (Mout) Mout[rt] = (int64_t)M;
+        }
+        __syncthreads();
     }
+}
+
+// Totals per replica id for the observables calls (same reduction as the
+// exchange step, so both give the same bits).
+__global__ __launch_bounds__(kExchangeThreads) void reduce_kernel(Lattice lat, int64_t *Bout, double *Fout,
+                                                                  int64_t *Mout) {
+    replica_totals(lat, Bout, Fout, Mout);
+}
+
+__global__ __launch_bounds__(kExchangeThreads) void exchange_kernel(const Lattice *__restrict__ lats, int tadv) {
+    const Lattice &lat = lats[blockIdx.x];
+    replica_totals(lat);
     const uint64_t k = lat.ctrs[1];
     __syncthreads();
-    for (int p = (int)(k & 1) + 2 * (int)threadIdx.x; p + 1 < lat.R; p += 512) {
+    for (int p = (int)(k & 1) + 2 * (int)threadIdx.x; p + 1 < lat.R; p += 2 * kExchangeThreads) {
         const int a = lat.t2r[p], b = lat.t2r[p + 1];
         const double delta = (lat.beta[p + 1] - lat.beta[p]) * (lat.E[b] - lat.E[a]);
         const Words w = philox10((uint32_t)p, (uint32_t)k, 0u, (kTagExch << 28) | lat.rho, lat.key0,
@@ -751,7 +771,7 @@ __global__ __launch_bounds__(256) void exchange_kernel(const Lattice *__restrict
     }
     __syncthreads();
     // one measurement per exchange step (Sec. 7), by temperature slot
-    for (int t = threadIdx.x; t < lat.R; t += 256) {
+    for (int t = threadIdx.x; t < lat.R; t += kExchangeThreads) {
         const int a = lat.t2r[t];
         const double e = lat.E[a], m = lat.Mr[a], m2 = m * m;
         double *o = lat.obs + 6 * (size_t)t;
@@ -906,13 +926,13 @@ hipError_t launch_energy(const Lattice &lat, hipStream_t s) {
 }
 
 hipError_t launch_reduce(const Lattice &lat, int64_t *B, double *F, int64_t *M, hipStream_t s) {
-    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, s, lat, B, F, M);
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kExchangeThreads), 0, s, lat, B, F, M);
     return hipGetLastError();
 }
 
 hipError_t launch_exchange(const Lattice *lats, int n, int tadv, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(exchange_kernel, dim3(n), dim3(256), 0, s, lats, tadv);
+    hipLaunchKernelGGL(exchange_kernel, dim3(n), dim3(kExchangeThreads), 0, s, lats, tadv);
     return hipGetLastError();
 }
 
