@@ -24,6 +24,8 @@ import re
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -390,20 +392,24 @@ def main():
     # the production shape, timed with events on the handle's stream.
     # One launch covers every replica (one stream); the production path
     # splits large half-sweeps over two streams, timed here as well.
+    # Median of 10 repetitions of 40 sweeps (80 half-sweeps) each.
     h = handles[-1]
-    n_roof = 200
+    n_roof, reps = 40, 10
 
     def half_sweep_us(streams):
         h.set_concurrency(streams)
         h.sweep(10, 0)
         stream.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        h.sweep(n_roof, 0)
-        e1.record(stream)
-        stream.synchronize()
-        return e0.elapsed_time(e1) * 1e3 / (2 * n_roof)
+        times = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            h.sweep(n_roof, 0)
+            e1.record(stream)
+            stream.synchronize()
+            times.append(e0.elapsed_time(e1) * 1e3 / (2 * n_roof))
+        return float(np.median(times))
 
     launch_us = half_sweep_us(1)
     split_us = half_sweep_us(2)
