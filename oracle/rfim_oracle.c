@@ -208,12 +208,12 @@ orc_t *orc_create(int L, int R, double J, double h, const float *fields,
         o->f[i] = fields[i];
         o->fs[i] = fields[i] > 0.0f ? 1 : -1;
         int x = site_x(o, i), y = site_y(o, i), z = site_z(o, i);
-        o->nb[6 * i + 0] = site_of(o, x + 1, y, z);
-        o->nb[6 * i + 1] = site_of(o, x - 1, y, z);
-        o->nb[6 * i + 2] = site_of(o, x, y + 1, z);
-        o->nb[6 * i + 3] = site_of(o, x, y - 1, z);
-        o->nb[6 * i + 4] = site_of(o, x, y, z + 1);
-        o->nb[6 * i + 5] = site_of(o, x, y, z - 1);
+        o->nb[6 * (size_t)i + 0] = site_of(o, x + 1, y, z);
+        o->nb[6 * (size_t)i + 1] = site_of(o, x - 1, y, z);
+        o->nb[6 * (size_t)i + 2] = site_of(o, x, y + 1, z);
+        o->nb[6 * (size_t)i + 3] = site_of(o, x, y - 1, z);
+        o->nb[6 * (size_t)i + 4] = site_of(o, x, y, z + 1);
+        o->nb[6 * (size_t)i + 5] = site_of(o, x, y, z - 1);
     }
     for (int t = 0; t < R; ++t) {
         o->T[t] = temps[t];
@@ -251,9 +251,9 @@ static void replica_components(const orc_t *o, int r, int64_t *B, double *F,
     double fsum = 0.0;
     for (int i = 0; i < o->N; ++i) {
         /* forward bonds +x, +y, +z: each bond once */
-        bonds += (int64_t)s[i] * s[o->nb[6 * i + 0]];
-        bonds += (int64_t)s[i] * s[o->nb[6 * i + 2]];
-        bonds += (int64_t)s[i] * s[o->nb[6 * i + 4]];
+        bonds += (int64_t)s[i] * s[o->nb[6 * (size_t)i + 0]];
+        bonds += (int64_t)s[i] * s[o->nb[6 * (size_t)i + 2]];
+        bonds += (int64_t)s[i] * s[o->nb[6 * (size_t)i + 4]];
         mag += s[i];
         fint += (int64_t)o->fs[i] * s[i];
         fsum += (double)o->f[i] * (double)s[i];
@@ -309,7 +309,7 @@ int orc_temps(const orc_t *o, double *T) {
 /* ------------------------------------------------------------------ */
 static int neighbour_sum(const orc_t *o, const int8_t *s, int i) {
     int n = 0;
-    for (int d = 0; d < 6; ++d) n += s[o->nb[6 * i + d]];
+    for (int d = 0; d < 6; ++d) n += s[o->nb[6 * (size_t)i + d]];
     return n;
 }
 

@@ -124,3 +124,75 @@ def test_large_lattices_match_oracle(rfim_mod, oracle_mod, L, R, sweeps, every, 
     assert np.array_equal(g.fourier(), want_f)
     g.close()
     o.close()
+
+
+def test_largest_lattice_sampled_replay(rfim_mod, oracle_mod):
+    """L = 1024, the largest size the library accepts (2^30 sites per
+    replica, 1 GiB of spins; site and sublattice offsets near 2^30 and
+    2^29).  The oracle cannot hold this lattice, so sampled sites are
+    replayed one by one from the oracle's Philox block function and its
+    threshold table (a small oracle with the same J, h, T): initial spins
+    from the INIT stream, then the colour-0 decisions of sweep 0, then the
+    colour-1 decisions on top of those.  Plus the energy/magnetisation
+    identities of the full state."""
+    L, J, h, T = 1024, 1.0, 1.0, 2.5
+    N = L ** 3
+    seed, rho = 48, 0
+    f = W.bimodal_fields(L, [47, L])
+    g = rfim_mod.Rfim(L, 1, J, h, f, np.array([T]), seed=seed)
+    g.sweep(1, 0)
+    s = g.spins()[0]
+    B, F, M = g.components()
+    assert M[0] == int(s.astype(np.int64).sum())
+    g.close()
+    small = oracle_mod.Oracle(8, 1, J, h, W.bimodal_fields(8, [0, 0]), [T])
+    thr, always = small.thresholds()
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+
+    def word(tag, c0, c1, c2, q):
+        return int(oracle_mod.philox4x32_10([c0, c1, c2, (tag << 28) | rho], key)[q])
+
+    def xyz(i):
+        return i % L, (i // L) % L, i // (L * L)
+
+    def site(x, y, z):
+        return (x % L) + L * ((y % L) + L * (z % L))
+
+    def nbrs(i):
+        x, y, z = xyz(i)
+        return [site(x + 1, y, z), site(x - 1, y, z), site(x, y + 1, z), site(x, y - 1, z),
+                site(x, y, z + 1), site(x, y, z - 1)]
+
+    init = {}
+
+    def s0(i):
+        if i not in init:
+            init[i] = 1 if word(1, i >> 2, 0, 0, i & 3) >= 2 ** 31 else -1
+        return init[i]
+
+    def decide(i, si, nsum, colour):
+        k = (si * nsum + 6) // 2
+        fb = 1 if si * f[i] > 0 else 0
+        cls = 2 * k + fb
+        j = i >> 1
+        u = word(2, j >> 2, colour, 0, j & 3)          # sweep 0: counter word 1 = 2*0 + colour
+        return -si if (always[cls] or u < int(thr[0, cls])) else si
+
+    after0 = {}
+
+    def s_after_colour0(i):                           # a colour-0 site after the first half-sweep
+        if i not in after0:
+            after0[i] = decide(i, s0(i), sum(s0(n) for n in nbrs(i)), 0)
+        return after0[i]
+
+    rng = np.random.default_rng(49)
+    checked = 0
+    for i in rng.integers(0, N, size=400).tolist() + [N - 1, N - 2, N // 2 + 1, 0, 1]:
+        x, y, z = xyz(i)
+        if (x + y + z) % 2 == 0:
+            want = s_after_colour0(i)
+        else:
+            want = decide(i, s0(i), sum(s_after_colour0(n) for n in nbrs(i)), 1)
+        assert int(s[i]) == want, (i, int(s[i]), want)
+        checked += 1
+    assert checked >= 400
