@@ -91,9 +91,23 @@ typedef struct rfim_params {
     int field_kind;         /* RFIM_FIELDS_AUTO / _BIMODAL / _CONTINUOUS */
 } rfim_params_t;
 
-/* As rfim_create with the extra parameters; hip_stream is a hipStream_t
- * owned by the caller (NULL: the handle creates its own). */
-rfim_t *rfim_create_ex(const rfim_params_t *params, void *hip_stream);
+/* Device memory provider for one handle.  alloc(bytes, ctx) returns device
+ * memory of at least `bytes` bytes, 16-byte aligned, usable from the
+ * handle's stream(s), or NULL (the call then fails with RFIM_ENOMEM);
+ * free(ptr, ctx) takes back a pointer alloc returned, after the handle's
+ * work on it has finished.  Both run on the thread that called into the
+ * library (create, rfim_set_measure, destroy).  A caching allocator (e.g.
+ * PyTorch's) can serve them. */
+typedef struct rfim_alloc {
+    void *(*alloc)(size_t bytes, void *ctx);
+    void (*free)(void *ptr, void *ctx);
+    void *ctx;
+} rfim_alloc_t;
+
+/* As rfim_create with the extra parameters.  alloc: where the handle's own
+ * device memory comes from (copied; NULL: hipMalloc / hipFree).  hip_stream
+ * is a hipStream_t owned by the caller (NULL: the handle creates its own). */
+rfim_t *rfim_create_ex(const rfim_params_t *params, const rfim_alloc_t *alloc, void *hip_stream);
 
 /*
  * n sweeps of all replicas; after every sweep that makes the global sweep

@@ -62,6 +62,7 @@ struct rfim {
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int concurrency = 0;            // see rfim_set_concurrency
+    rfim_alloc_t alloc = {nullptr, nullptr, nullptr};   // device memory provider (rfim_create_ex)
     // optional Fourier measurement (rfim_set_measure)
     int measure = 0;
     int32_t *d_fpart = nullptr;
@@ -126,19 +127,42 @@ struct rfim {
 
 namespace {
 
+// The handle's own device memory, from its provider or hipMalloc.
+int dev_alloc(rfim *h, void **p, size_t bytes) {
+    *p = nullptr;
+    if (h->alloc.alloc) {
+        *p = h->alloc.alloc(bytes, h->alloc.ctx);
+        if (!*p) return fail(RFIM_ENOMEM, "device memory provider returned NULL for %zu bytes", bytes);
+        return RFIM_OK;
+    }
+    const hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(RFIM_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    return RFIM_OK;
+}
+
+void dev_free(rfim *h, void *p) {
+    if (!p) return;
+    if (h->alloc.free)
+        h->alloc.free(p, h->alloc.ctx);
+    else
+        (void)hipFree(p);
+}
+
 void free_device(rfim *h) {
     void *ptrs[] = {h->d_spins, h->d_fbits, h->d_fhf, h->d_fraw, h->d_betaf, h->d_thr,
                     h->d_beta,  h->d_part,  h->d_E,   h->d_t2r,  h->d_r2t,   h->d_att,
                     h->d_acc,   h->d_ctrs,  h->d_B,   h->d_M,    h->d_F,     h->d_Mr,
                     h->d_obs};
-    for (void *p : ptrs)
-        if (p) (void)hipFree(p);
-    if (h->d_lat) (void)hipFree(h->d_lat);
-    if (h->d_smap) (void)hipFree(h->d_smap);
-    if (h->d_rmap) (void)hipFree(h->d_rmap);
-    if (h->d_fpart) (void)hipFree(h->d_fpart);
-    if (h->d_trig) (void)hipFree(h->d_trig);
-    if (h->d_fobs) (void)hipFree(h->d_fobs);
+    for (void *p : ptrs) dev_free(h, p);
+    dev_free(h, h->d_lat);
+    dev_free(h, h->d_smap);
+    dev_free(h, h->d_rmap);
+    dev_free(h, h->d_fpart);
+    dev_free(h, h->d_trig);
+    dev_free(h, h->d_fobs);
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);
     if (h->aux) (void)hipStreamDestroy(h->aux);
@@ -252,8 +276,8 @@ int alloc_device(rfim *h) {
     h->nblk = rfim_dev::blocks_per_replica(h->L, h->mode, h->nw, h->wg);
 #define ALLOC(ptr, bytes)                                                                \
     do {                                                                                 \
-        hipError_t e_ = hipMalloc((void **)&(ptr), (bytes));                             \
-        if (e_ != hipSuccess) return fail(RFIM_ENOMEM, "hipMalloc(%zu): %s", (size_t)(bytes), hipGetErrorString(e_)); \
+        int rc_ = dev_alloc(h, (void **)&(ptr), (bytes));                                \
+        if (rc_) return rc_;                                                             \
     } while (0)
     ALLOC(h->d_spins, Rc * N);
     if (h->kind == 0) {
@@ -574,10 +598,15 @@ extern "C" {
 
 const char *rfim_last_error(void) { return g_error.c_str(); }
 
-rfim_t *rfim_create_ex(const rfim_params_t *params, void *hip_stream) {
+rfim_t *rfim_create_ex(const rfim_params_t *params, const rfim_alloc_t *alloc, void *hip_stream) {
+    if (alloc && (!alloc->alloc || !alloc->free)) {
+        fail(RFIM_EINVAL, "a device memory provider needs both alloc and free");
+        return nullptr;
+    }
     int err = 0;
     rfim *h = create_impl(params, hip_stream, &err);
     if (!h) return nullptr;
+    if (alloc) h->alloc = *alloc;
     if (init_device(h)) {
         std::string msg = g_error;
         destroy_impl(h);
@@ -601,7 +630,7 @@ rfim_t *rfim_create(int L, int R, double J, double h, const float *fields, const
     p.seed = seed;
     p.realization = 0;
     p.field_kind = RFIM_FIELDS_AUTO;
-    return rfim_create_ex(&p, nullptr);
+    return rfim_create_ex(&p, nullptr, nullptr);
 }
 
 void rfim_destroy(rfim_t *h) {
@@ -887,13 +916,13 @@ int rfim_set_measure(rfim_t *h, int flags) {
     if (flags & ~RFIM_MEASURE_FOURIER) return fail(RFIM_EINVAL, "unknown measurement flags %d", flags);
     if ((flags & RFIM_MEASURE_FOURIER) && !h->d_fpart) {
         const size_t L = (size_t)h->L, Rc = (size_t)h->R_cap;
-        if (hipMalloc((void **)&h->d_fpart, Rc * L * 2 * L * sizeof(int32_t)) != hipSuccess ||
-            hipMalloc((void **)&h->d_trig, 2 * L * sizeof(double)) != hipSuccess ||
-            hipMalloc((void **)&h->d_fobs, Rc * 2 * sizeof(double)) != hipSuccess) {
+        if (dev_alloc(h, (void **)&h->d_fpart, Rc * L * 2 * L * sizeof(int32_t)) ||
+            dev_alloc(h, (void **)&h->d_trig, 2 * L * sizeof(double)) ||
+            dev_alloc(h, (void **)&h->d_fobs, Rc * 2 * sizeof(double))) {
             (void)hipGetLastError();
-            if (h->d_fpart) (void)hipFree(h->d_fpart);
-            if (h->d_trig) (void)hipFree(h->d_trig);
-            if (h->d_fobs) (void)hipFree(h->d_fobs);
+            dev_free(h, h->d_fpart);
+            dev_free(h, h->d_trig);
+            dev_free(h, h->d_fobs);
             h->d_fpart = nullptr;
             h->d_trig = nullptr;
             h->d_fobs = nullptr;
@@ -1034,7 +1063,7 @@ rfim_t *rfim_load(const void *buf, size_t len, void *hip_stream) {
     p += N * 4;
     prm.temps = T.data();
     prm.fields = f.data();
-    rfim *h = rfim_create_ex(&prm, hip_stream);
+    rfim *h = rfim_create_ex(&prm, nullptr, hip_stream);
     if (!h) return nullptr;
     int rc = rfim_set_spins(h, (const int8_t *)p);
     p += (size_t)hd.R * N;

@@ -50,6 +50,37 @@ class rfim_params_t(C.Structure):
                 ("seed", C.c_uint64), ("realization", C.c_uint32), ("field_kind", C.c_int)]
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class rfim_alloc_t(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
+def torch_allocator(stream=None) -> rfim_alloc_t:
+    """A device memory provider backed by PyTorch's caching allocator (on
+    `stream`, a torch.cuda.Stream, or torch's current stream).  The caller
+    keeps the returned structure alive as long as the handle it serves."""
+    import torch
+
+    device = torch.cuda.current_device()
+
+    def alloc(nbytes, _ctx):
+        try:
+            return int(torch.cuda.caching_allocator_alloc(int(nbytes), device, stream))
+        except Exception:            # out of memory: the library reports RFIM_ENOMEM
+            return None
+
+    def free(ptr, _ctx):
+        try:
+            torch.cuda.caching_allocator_delete(int(ptr))
+        except Exception:            # interpreter shutdown: nothing left to return to
+            pass
+
+    return rfim_alloc_t(ALLOC_FN(alloc), FREE_FN(free), None)
+
+
 _lib = None
 
 
@@ -69,7 +100,7 @@ def load_library(path: str = LIB_PATH):
     vp, i32, i64, u64, dbl, sz = C.c_void_p, C.c_int, C.c_int64, C.c_uint64, C.c_double, C.c_size_t
     sig = {
         "rfim_create": (vp, [i32, i32, dbl, dbl, vp, vp, u64]),
-        "rfim_create_ex": (vp, [C.POINTER(rfim_params_t), vp]),
+        "rfim_create_ex": (vp, [C.POINTER(rfim_params_t), C.POINTER(rfim_alloc_t), vp]),
         "rfim_sweep": (i32, [vp, i64, i32]),
         "rfim_energies": (i32, [vp, vp]),
         "rfim_adapt_temps": (i32, [vp, i32, i64, i32, dbl, i32, i32]),
@@ -152,7 +183,7 @@ def rfim_create(L, R, J, h, fields, temps, seed):
 
 
 def rfim_create_ex(L, R, J, h, fields, temps, seed=0, realization=0, field_kind=FIELDS_AUTO,
-                   R_cap=0, stream=None):
+                   R_cap=0, stream=None, alloc=None):
     f = np.ascontiguousarray(fields, dtype=np.float32).reshape(-1)
     T = np.ascontiguousarray(temps, dtype=np.float64).reshape(-1)
     if f.size != int(L) ** 3 or T.size != int(R):
@@ -160,7 +191,7 @@ def rfim_create_ex(L, R, J, h, fields, temps, seed=0, realization=0, field_kind=
     prm = rfim_params_t(int(L), int(R), int(R_cap), float(J), float(h), f.ctypes.data,
                         T.ctypes.data, int(seed) & 0xFFFFFFFFFFFFFFFF, int(realization),
                         int(field_kind))
-    return load_library().rfim_create_ex(C.byref(prm), stream)
+    return load_library().rfim_create_ex(C.byref(prm), C.byref(alloc) if alloc is not None else None, stream)
 
 
 def rfim_sweep(handle, n, exchange_every):
@@ -188,7 +219,9 @@ class Rfim:
     """One disorder realization on the GPU (owns a librfim handle)."""
 
     def __init__(self, L, R, J, h, fields, temps, seed=0, realization=0, field_kind=FIELDS_AUTO,
-                 R_cap=0, stream=None):
+                 R_cap=0, stream=None, allocator=None):
+        """allocator: None (the library's hipMalloc), "torch" (PyTorch's
+        caching allocator on `stream`) or an rfim_alloc_t."""
         self.L = int(L)
         self.N = self.L ** 3
         self._torch_stream = None
@@ -196,8 +229,11 @@ class Rfim:
         if stream is not None:
             self._torch_stream = stream
             sptr = C.c_void_p(int(stream.cuda_stream))
+        if allocator == "torch":
+            allocator = torch_allocator(stream)
+        self._alloc = allocator           # the callbacks must outlive the handle
         self._h = rfim_create_ex(L, R, J, h, fields, temps, seed, realization, field_kind, R_cap,
-                                 sptr)
+                                 sptr, allocator)
         if not self._h:
             raise ValueError(last_error())
 

@@ -278,3 +278,28 @@ def test_fourier_measurement_matches_oracle_replay(rfim_mod, oracle_mod, L, R, s
     with pytest.raises(rfim_mod.RfimError):
         g.set_measure(2)
     g.close()
+
+
+def test_torch_allocator_serves_the_handle(rfim_mod, oracle_mod):
+    """With PyTorch's caching allocator as the device memory provider the
+    handle's buffers come from torch (its allocated bytes grow by at least
+    the spins), the chain is the oracle's, and destroying the handle gives
+    the memory back."""
+    import torch
+
+    L, R = 16, 5
+    f = W.bimodal_fields(L, [24, L])
+    T = W.linear_temps(R, 1.0, 5.0)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    g = rfim_mod.Rfim(L, R, 1.0, 1.5, f, T, seed=6, stream=s, allocator="torch")
+    assert torch.cuda.memory_allocated() - before >= R * L ** 3
+    g.set_measure(rfim_mod.MEASURE_FOURIER)
+    o = oracle_mod.Oracle(L, R, 1.0, 1.5, f, T, seed=6)
+    g.sweep(30, 10)
+    o.sweep(30, 10)
+    assert_same_state(g, o, "torch allocator")
+    g.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == before
