@@ -33,9 +33,13 @@
  *
  * Ownership and threading.  The caller owns every host array; inputs are
  * copied, outputs are written into caller buffers of the documented size.
- * A handle owns its device memory and issues all work on one HIP stream
- * (its own, or one set with rfim_set_stream).  One handle is used from one
- * thread at a time; different handles are independent.
+ * A handle owns its device memory (from hipMalloc, or from a provider given
+ * to rfim_create_ex) and orders all its work on one HIP stream (its own, or
+ * one set with rfim_set_stream); inside large streaming sweeps it forks half
+ * of the replicas onto a second stream of its own and joins it back before
+ * the exchange step (rfim_set_concurrency), so callers see one stream.  One
+ * handle is used from one thread at a time; different handles are
+ * independent.
  *
  * Errors.  Calls return RFIM_OK (0) or a negative status; constructors
  * return NULL.  rfim_last_error() gives a thread-local message for the last
