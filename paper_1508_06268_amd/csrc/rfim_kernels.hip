@@ -383,35 +383,46 @@ __device__ __forceinline__ uint32_t continuous_flips(uint32_t U, uint32_t Wown, 
     return __umul24(acc, 0x204081u) & 0x01010101u;
 }
 
-// One chunk's half-sweep update; returns the new own words (and the loaded
-// words the energy pass reuses).
-template <int KIND, int NW, bool NEV, class PO, class PC, class PB, class PF>
-__device__ __forceinline__ uint32_t chunk_update(const Lattice &lat, const uint32_t *sthr, uint32_t never,
-                                                 PO own, PC oth,
-                                                 PB fb_own, PF hf_own, uint32_t j0, uint32_t g0,
-                                                 uint32_t colour, uint32_t c1, uint32_t r, float beta,
-                                                 uint32_t (&W)[NW], uint32_t (&U)[NW],
-                                                 uint32_t (&Wnew)[NW], uint32_t (&F4)[NW]) {
-    const Chunk c = chunk_geometry<NW>(j0, colour, (uint32_t)lat.L, (uint32_t)lat.log2L, (uint32_t)lat.half);
-    // Every load of the chunk is issued before any arithmetic (the scheduling
-    // barrier keeps the compiler from sinking one next to its use): with many
-    // realizations in a launch the fields and rows miss in L2, and a load
-    // issued per Philox block would expose the memory latency each time.
+// The words a chunk's half-sweep update reads: its own words, the
+// other-colour words around it and its fields.
+template <int KIND, int NW> struct ChunkIn {
+    Chunk c;
     uint32_t Wown[NW];
-    load_words<NW>(own, j0, Wown);
     Around<NW> a;
-    load_around<NW>(oth, j0, c, a);
-    f32x4 HF[NW];
+    f32x4 HF[NW];   // continuous fields (KIND 1)
+};
+
+// Issue every load of a chunk (F4: the +-1 field bits, KIND 0).  Callers put
+// a scheduling barrier after it so the compiler does not sink a load next to
+// its use: with many realizations in a launch the fields and rows miss in
+// L2, and a load issued per Philox block would expose the memory latency
+// each time.
+template <int KIND, int NW, class PO, class PC, class PB, class PF>
+__device__ __forceinline__ void chunk_load(const Lattice &lat, PO own, PC oth, PB fb_own, PF hf_own, uint32_t j0,
+                                           uint32_t colour, ChunkIn<KIND, NW> &in, uint32_t (&F4)[NW]) {
+    in.c = chunk_geometry<NW>(j0, colour, (uint32_t)lat.L, (uint32_t)lat.log2L, (uint32_t)lat.half);
+    load_words<NW>(own, j0, in.Wown);
+    load_around<NW>(oth, j0, in.c, in.a);
     if (KIND == 0) {
         load_words<NW>(fb_own, j0, F4);
     } else {
 #pragma unroll
-        for (int w = 0; w < NW; ++w) HF[w] = *(typename rebind_ptr<PF, const f32x4>::type)(hf_own + j0 + 4u * w);
+        for (int w = 0; w < NW; ++w)
+            in.HF[w] = *(typename rebind_ptr<PF, const f32x4>::type)(hf_own + j0 + 4u * w);
     }
-    __builtin_amdgcn_sched_barrier(0);
-    neighbour_sums<NW>(c, a, U);
+}
+
+// The flip decisions of a loaded chunk; returns nonzero if any site flips,
+// with the new own words in Wnew (and the other-colour words and neighbour
+// sums the energy pass reuses in W and U).
+template <int KIND, int NW, bool NEV>
+__device__ __forceinline__ uint32_t chunk_flip(const Lattice &lat, const uint32_t *sthr, uint32_t never,
+                                               const ChunkIn<KIND, NW> &in, const uint32_t (&F4)[NW],
+                                               uint32_t g0, uint32_t c1, uint32_t r, float beta,
+                                               uint32_t (&W)[NW], uint32_t (&U)[NW], uint32_t (&Wnew)[NW]) {
+    neighbour_sums<NW>(in.c, in.a, U);
 #pragma unroll
-    for (int w = 0; w < NW; ++w) W[w] = a.W[w];
+    for (int w = 0; w < NW; ++w) W[w] = in.a.W[w];
     const uint32_t c3 = (kTagSweep << 28) | lat.rho;
     uint32_t any = 0;
 #pragma unroll
@@ -419,29 +430,39 @@ __device__ __forceinline__ uint32_t chunk_update(const Lattice &lat, const uint3
         const Words rw = philox10(g0 + (uint32_t)w, c1, r, c3, lat.key0, lat.key1);
         uint32_t fl;
         if (KIND == 0) {
-            fl = bimodal_flips<NEV>(sthr, U[w], Wown[w], F4[w], rw, never);
+            fl = bimodal_flips<NEV>(sthr, U[w], in.Wown[w], F4[w], rw, never);
         } else {
-            fl = continuous_flips(U[w], Wown[w], HF[w], 2.0f * lat.Jf, -2.0f * 1.44269504088896341f * beta, rw);
+            fl = continuous_flips(U[w], in.Wown[w], in.HF[w], 2.0f * lat.Jf, -2.0f * 1.44269504088896341f * beta,
+                                  rw);
         }
         any |= fl;
-        Wnew[w] = Wown[w] ^ fl;
+        Wnew[w] = in.Wown[w] ^ fl;
     }
     return any;
 }
 
-// chunk_update with the never-class correction only where this slot has
-// such classes (a wave-uniform branch between two copies).
+// chunk_flip with the never-class correction only where this slot has such
+// classes (a wave-uniform branch between two copies).
+template <int KIND, int NW>
+__device__ __forceinline__ uint32_t chunk_flip_any(const Lattice &lat, const uint32_t *sthr, uint32_t never,
+                                                   const ChunkIn<KIND, NW> &in, const uint32_t (&F4)[NW],
+                                                   uint32_t g0, uint32_t c1, uint32_t r, float beta,
+                                                   uint32_t (&W)[NW], uint32_t (&U)[NW], uint32_t (&Wnew)[NW]) {
+    if (KIND == 0 && never != 0u) return chunk_flip<KIND, NW, true>(lat, sthr, never, in, F4, g0, c1, r, beta, W, U, Wnew);
+    return chunk_flip<KIND, NW, false>(lat, sthr, never, in, F4, g0, c1, r, beta, W, U, Wnew);
+}
+
+// One chunk's half-sweep update: load, then flip.
 template <int KIND, int NW, class PO, class PC, class PB, class PF>
 __device__ __forceinline__ uint32_t chunk_update_any(const Lattice &lat, const uint32_t *sthr, uint32_t never,
                                                      PO own, PC oth, PB fb_own, PF hf_own, uint32_t j0,
                                                      uint32_t g0, uint32_t colour, uint32_t c1, uint32_t r,
                                                      float beta, uint32_t (&W)[NW], uint32_t (&U)[NW],
                                                      uint32_t (&Wnew)[NW], uint32_t (&F4)[NW]) {
-    if (KIND == 0 && never != 0u)
-        return chunk_update<KIND, NW, true>(lat, sthr, never, own, oth, fb_own, hf_own, j0, g0, colour, c1, r,
-                                            beta, W, U, Wnew, F4);
-    return chunk_update<KIND, NW, false>(lat, sthr, never, own, oth, fb_own, hf_own, j0, g0, colour, c1, r,
-                                         beta, W, U, Wnew, F4);
+    ChunkIn<KIND, NW> in;
+    chunk_load<KIND, NW>(lat, own, oth, fb_own, hf_own, j0, colour, in, F4);
+    __builtin_amdgcn_sched_barrier(0);
+    return chunk_flip_any<KIND, NW>(lat, sthr, never, in, F4, g0, c1, r, beta, W, U, Wnew);
 }
 
 // Energy pieces of a chunk of colour-1 sites and the colour-0 sites of the
@@ -513,7 +534,7 @@ template <int KIND, int NW, int ENERGY, bool BATCH>
 __global__ __launch_bounds__(256) void sweep_pow2(Lattice lat0, const Lattice *__restrict__ lats,
                                                    const uint2 *__restrict__ map, int colour, int toff,
                                                    int remap, int lwpr, int r0) {
-    __shared__ uint32_t sthr[32];
+    __shared__ uint32_t sthr[32 * 4];   // one table per wave
     uint32_t blk = blockIdx.x;
     if (remap) {
         // consecutive block ids go round-robin to the 8 XCDs; give each XCD a
@@ -531,13 +552,6 @@ __global__ __launch_bounds__(256) void sweep_pow2(Lattice lat0, const Lattice *_
         gb = blk & ((1u << lwpr) - 1u);
     }
     const Lattice &lat = BATCH ? lats[map[blk].x >> 16] : lat0;
-    const int slot = gptr(lat.r2t)[r];
-    uint32_t never = 0;
-    if (KIND == 0) {
-        if (threadIdx.x < 32) sthr[threadIdx.x] = gptr(lat.thr)[slot * 32 + threadIdx.x];
-        __syncthreads();
-        never = __builtin_amdgcn_readfirstlane(sthr[31]);
-    }
     const uint32_t g0 = (gb * blockDim.x + threadIdx.x) * NW;   // first Philox block
     const uint32_t j0 = 4u * g0;
     const uint32_t col = (uint32_t)colour;
@@ -546,12 +560,28 @@ __global__ __launch_bounds__(256) void sweep_pow2(Lattice lat0, const Lattice *_
     GAS const uint8_t *oth = spins + (size_t)r * lat.N + (size_t)(1 - col) * lat.half;
     GAS const uint8_t *fbits = gptr(lat.fbits);
     GAS const float *fhf = gptr(lat.fhf), *fraw = gptr(lat.fraw);
+    // The chunk's loads go out first; the slot's table (r2t, then thr) is
+    // fetched while they are in flight.  Each wave keeps its own copy of the
+    // table, so no workgroup barrier stands between the two.
+    ChunkIn<KIND, NW> in;
+    uint32_t F4[NW];
+    chunk_load<KIND, NW>(lat, own, oth, fbits + (size_t)col * lat.half, fhf + (size_t)col * lat.half, j0, col, in,
+                         F4);
+    __builtin_amdgcn_sched_barrier(0);
+    const int slot = gptr(lat.r2t)[r];
     const uint32_t t = (uint32_t)(gptr(lat.ctrs)[0] + (uint64_t)toff);
+    uint32_t *wthr = sthr + 32 * (threadIdx.x >> 6);
+    uint32_t never = 0;
+    if (KIND == 0) {
+        if ((threadIdx.x & 63u) < 32u) wthr[threadIdx.x & 31u] = gptr(lat.thr)[slot * 32 + (threadIdx.x & 31u)];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        never = __builtin_amdgcn_readfirstlane(wthr[31]);
+    }
     const float beta = KIND == 1 ? gptr(lat.betaf)[slot] : 0.0f;
-    uint32_t W[NW], U[NW], Wnew[NW], F4[NW];
-    const uint32_t any = chunk_update_any<KIND, NW>(lat, sthr, never, own, oth, fbits + (size_t)col * lat.half,
-                                                fhf + (size_t)col * lat.half, j0, g0, col, 2u * t + col, r,
-                                                beta, W, U, Wnew, F4);
+    uint32_t W[NW], U[NW], Wnew[NW];
+    const uint32_t any = chunk_flip_any<KIND, NW>(lat, wthr, never, in, F4, g0, 2u * t + col, r, beta, W, U, Wnew);
     if (any) store_words<NW>(own, j0, Wnew);
     if (ENERGY) {
         int ksum = 0, upsum = 0, eqsum = 0;
@@ -694,30 +724,61 @@ __device__ __forceinline__ double energy_of(const Lattice &lat, double B, double
 constexpr int kExchangeThreads = 1024;
 
 // Energy and magnetisation of every replica from its partials (B, F, M per
-// block, block-major).  Thread (g, r) sums blocks [g per, (g+1) per) of
-// replica r in order -- consecutive threads take consecutive replicas, so
-// every load is coalesced, and all of a thread's loads are independent --
-// then one thread per replica adds its G range sums in order.  The order is
-// fixed for a given launch shape and replica count, so FP64 totals are
+// block, block-major).  Thread (g, r) sums blocks [g per, min((g+1) per,
+// nblk)) of replica r in order -- consecutive threads take consecutive
+// replicas, so every load is coalesced -- issuing up to 8 blocks' loads
+// before it adds any, so the range costs a few memory round trips rather than
+// one per block; then one thread per replica adds its G range sums in order.
+// nblk need not be a power of two (the generic kernel's is not).  The order
+// is fixed for a given launch shape and replica count, so FP64 totals are
 // reproducible.  Writes E and Mr, and B, F, M when asked (observables).
+template <int B>
+__device__ __forceinline__ void sum_range(GAS const double *pp, size_t qstride, int q_end, double &b, double &f,
+                                          double &m) {
+    for (int q0 = 0; q0 < q_end; q0 += B) {
+        // loads past the range re-read its last block (always in bounds, no
+        // branch between the loads); their adds are skipped
+        double vb[B], vf[B], vm[B];
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            GAS const double *pq = pp + (size_t)min(q0 + j, q_end - 1) * qstride;
+            vb[j] = pq[0];
+            vf[j] = pq[1];
+            vm[j] = pq[2];
+        }
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            const bool in = q0 + j < q_end;
+            b = in ? b + vb[j] : b;
+            f = in ? f + vf[j] : f;
+            m = in ? m + vm[j] : m;
+        }
+    }
+}
+
 __device__ __forceinline__ void replica_totals(const Lattice &lat, int64_t *Bout = nullptr,
                                                double *Fout = nullptr, int64_t *Mout = nullptr) {
     __shared__ double red[kExchangeThreads * 3];
     const int R = lat.R, nblk = lat.nblk;
     int G = 1;
     while (2 * G <= nblk && 2 * G <= 64 && (long long)R * 2 * G <= kExchangeThreads) G *= 2;
-    const int tile = kExchangeThreads / G, per = nblk / G;   // nblk and G are powers of two
+    const int tile = kExchangeThreads / G, per = (nblk + G - 1) / G;
     const int g = (int)threadIdx.x / tile, rl = (int)threadIdx.x % tile;
+    const int q_end = min(per, nblk - g * per);   // blocks in this thread's range (may be <= 0)
+    const size_t qstride = (size_t)lat.pstride * 3;
     for (int r0 = 0; r0 < R; r0 += tile) {
         const int r = r0 + rl;
         double b = 0.0, f = 0.0, m = 0.0;
         if (r < R) {
-            const double *pp = lat.part + ((size_t)g * per * lat.pstride + r) * 3;
-            for (int q = 0; q < per; ++q) {
-                b += pp[(size_t)q * lat.pstride * 3 + 0];
-                f += pp[(size_t)q * lat.pstride * 3 + 1];
-                m += pp[(size_t)q * lat.pstride * 3 + 2];
-            }
+            GAS const double *pp = gptr(lat.part) + ((size_t)g * per * lat.pstride + r) * 3;
+            if (per == 1)       // the batch width follows the range (uniform per block)
+                sum_range<1>(pp, qstride, q_end, b, f, m);
+            else if (per == 2)
+                sum_range<2>(pp, qstride, q_end, b, f, m);
+            else if (per <= 4)
+                sum_range<4>(pp, qstride, q_end, b, f, m);
+            else
+                sum_range<8>(pp, qstride, q_end, b, f, m);
         }
         red[3 * threadIdx.x + 0] = b;
         red[3 * threadIdx.x + 1] = f;

@@ -24,6 +24,8 @@ def test_plain_l8_full_run(rfim_mod, oracle_mod):
     (4, 5, 1.5, 200, 7),       # generic kernel
     (6, 3, 2.0, 100, 5),       # generic kernel, dE = 0 ties
     (10, 4, 1.0, 30, 10),      # generic kernel, rows not a multiple of 4 groups
+    (18, 3, 2.0, 20, 5),       # generic kernel, 3 energy blocks per replica
+    (24, 5, 1.5, 20, 4),       # generic kernel, 7 energy blocks (not a power of two)
     (16, 8, 2.25, 60, 10),     # power-of-two kernel, several workgroups per replica
     (32, 6, 1.0, 20, 10),
 ])
@@ -248,6 +250,31 @@ def test_forced_split_small_lattice(rfim_mod, oracle_mod):
     assert_same_state(g, o, "L=32 R=7 two streams")
     with pytest.raises(rfim_mod.RfimError):
         g.set_concurrency(3)
+    g.close()
+
+
+@pytest.mark.parametrize("L,R,kind", [(18, 3, "b"), (24, 4, "b"), (36, 3, "b"), (24, 3, "g")])
+def test_generic_kernel_energies_any_block_count(rfim_mod, oracle_mod, L, R, kind):
+    """The generic kernel's energy partials come in min(64, ceil(L^3/2048))
+    blocks per replica, which is not a power of two at these L (3, 7, 23):
+    every block must enter the total.  From identical random states the
+    bond, field and magnetisation sums equal the oracle's (the field sum to
+    rounding for Gaussian fields), and so do the energies."""
+    f = W.bimodal_fields(L, [48, L]) if kind == "b" else W.gaussian_fields(L, [48, L])
+    T = W.linear_temps(R, 1.0, 4.0)
+    g, o = make_pair(rfim_mod, oracle_mod, L, R, 1.0, 1.25, f, T, seed=13)
+    s = W.random_spins(R, L, [48, L, 1])
+    g.set_spins(s)
+    o.set_spins(s)
+    gb, gf, gm = g.components()
+    ob, of, om = o.components()
+    assert np.array_equal(gb, ob) and np.array_equal(gm, om)
+    if kind == "b":
+        assert np.array_equal(gf, of)
+        assert np.array_equal(g.energies(), o.energies())
+    else:
+        assert np.allclose(gf, of, rtol=1e-12, atol=1e-9)
+        assert np.allclose(g.energies(), o.energies(), rtol=1e-12, atol=1e-9)
     g.close()
 
 
