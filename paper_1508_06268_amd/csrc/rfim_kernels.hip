@@ -534,7 +534,7 @@ template <int KIND, int NW, int ENERGY, bool BATCH>
 __global__ __launch_bounds__(256) void sweep_pow2(Lattice lat0, const Lattice *__restrict__ lats,
                                                    const uint2 *__restrict__ map, int colour, int toff,
                                                    int remap, int lwpr, int r0) {
-    __shared__ uint32_t sthr[32 * 4];   // one table per wave
+    __shared__ uint32_t sthr[32];
     uint32_t blk = blockIdx.x;
     if (remap) {
         // consecutive block ids go round-robin to the 8 XCDs; give each XCD a
@@ -561,8 +561,8 @@ __global__ __launch_bounds__(256) void sweep_pow2(Lattice lat0, const Lattice *_
     GAS const uint8_t *fbits = gptr(lat.fbits);
     GAS const float *fhf = gptr(lat.fhf), *fraw = gptr(lat.fraw);
     // The chunk's loads go out first; the slot's table (r2t, then thr) is
-    // fetched while they are in flight.  Each wave keeps its own copy of the
-    // table, so no workgroup barrier stands between the two.
+    // fetched while they are in flight, so the workgroup's barrier on the
+    // table costs the longer of the two chains rather than their sum.
     ChunkIn<KIND, NW> in;
     uint32_t F4[NW];
     chunk_load<KIND, NW>(lat, own, oth, fbits + (size_t)col * lat.half, fhf + (size_t)col * lat.half, j0, col, in,
@@ -570,18 +570,15 @@ __global__ __launch_bounds__(256) void sweep_pow2(Lattice lat0, const Lattice *_
     __builtin_amdgcn_sched_barrier(0);
     const int slot = gptr(lat.r2t)[r];
     const uint32_t t = (uint32_t)(gptr(lat.ctrs)[0] + (uint64_t)toff);
-    uint32_t *wthr = sthr + 32 * (threadIdx.x >> 6);
     uint32_t never = 0;
     if (KIND == 0) {
-        if ((threadIdx.x & 63u) < 32u) wthr[threadIdx.x & 31u] = gptr(lat.thr)[slot * 32 + (threadIdx.x & 31u)];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        never = __builtin_amdgcn_readfirstlane(wthr[31]);
+        if (threadIdx.x < 32u) sthr[threadIdx.x] = gptr(lat.thr)[slot * 32 + threadIdx.x];
+        __syncthreads();
+        never = __builtin_amdgcn_readfirstlane(sthr[31]);
     }
     const float beta = KIND == 1 ? gptr(lat.betaf)[slot] : 0.0f;
     uint32_t W[NW], U[NW], Wnew[NW];
-    const uint32_t any = chunk_flip_any<KIND, NW>(lat, wthr, never, in, F4, g0, 2u * t + col, r, beta, W, U, Wnew);
+    const uint32_t any = chunk_flip_any<KIND, NW>(lat, sthr, never, in, F4, g0, 2u * t + col, r, beta, W, U, Wnew);
     if (any) store_words<NW>(own, j0, Wnew);
     if (ENERGY) {
         int ksum = 0, upsum = 0, eqsum = 0;
@@ -757,7 +754,8 @@ __device__ __forceinline__ void sum_range(GAS const double *pp, size_t qstride, 
 }
 
 __device__ __forceinline__ void replica_totals(const Lattice &lat, int64_t *Bout = nullptr,
-                                               double *Fout = nullptr, int64_t *Mout = nullptr) {
+                                               double *Fout = nullptr, int64_t *Mout = nullptr,
+                                               double *sE = nullptr, double *sM = nullptr) {
     __shared__ double red[kExchangeThreads * 3];
     const int R = lat.R, nblk = lat.nblk;
     int G = 1;
@@ -793,8 +791,13 @@ __device__ __forceinline__ void replica_totals(const Lattice &lat, int64_t *Bout
                 M += rr[2];
             }
             const int rt = r0 + (int)threadIdx.x;
-            lat.E[rt] = energy_of(lat, B, F);
+            const double E = energy_of(lat, B, F);
+            lat.E[rt] = E;
             lat.Mr[rt] = M;
+            if (sE) {
+                sE[rt] = E;
+                sM[rt] = M;
+            }
             if (Bout) Bout[rt] = (int64_t)B;
             if (Fout) Fout[rt] = F;
             if (Mout) Mout[rt] = (int64_t)M;
@@ -810,38 +813,101 @@ __global__ __launch_bounds__(kExchangeThreads) void reduce_kernel(Lattice lat, i
     replica_totals(lat, Bout, Fout, Mout);
 }
 
+// The decision for pair (p, p+1) of exchange step k: Philox word pair ->
+// a uniform double in [0, 1) with 53 random bits, accepted if Delta >= 0 or
+// u < e^Delta.
+__device__ __forceinline__ bool exchange_accept(const Lattice &lat, int p, uint64_t k, double delta) {
+    const Words w = philox10((uint32_t)p, (uint32_t)k, 0u, (kTagExch << 28) | lat.rho, lat.key0, lat.key1);
+    const double u53 = ((double)(w.w0 >> 11) * 4294967296.0 + (double)w.w1) * 0x1p-53;
+    return delta >= 0.0 || u53 < exp(delta);
+}
+
+// One exchange step per workgroup (one realization each).  Up to
+// kExchangeThreads replicas the step runs out of LDS: the permutation, the
+// inverse temperatures, the slot's observable sums and the pair counters are
+// loaded together with the energy partials, so the whole step costs about
+// two memory round trips; more replicas take the same steps through global
+// memory.
 __global__ __launch_bounds__(kExchangeThreads) void exchange_kernel(const Lattice *__restrict__ lats, int tadv) {
+    __shared__ double sE[kExchangeThreads], sM[kExchangeThreads];
+    __shared__ int32_t st2r[kExchangeThreads];
     const Lattice &lat = lats[blockIdx.x];
-    replica_totals(lat);
     const uint64_t k = lat.ctrs[1];
-    __syncthreads();
-    for (int p = (int)(k & 1) + 2 * (int)threadIdx.x; p + 1 < lat.R; p += 2 * kExchangeThreads) {
-        const int a = lat.t2r[p], b = lat.t2r[p + 1];
-        const double delta = (lat.beta[p + 1] - lat.beta[p]) * (lat.E[b] - lat.E[a]);
-        const Words w = philox10((uint32_t)p, (uint32_t)k, 0u, (kTagExch << 28) | lat.rho, lat.key0,
-                                 lat.key1);
-        const double u53 = ((double)(w.w0 >> 11) * 4294967296.0 + (double)w.w1) * 0x1p-53;
-        lat.att[p] += 1;
-        if (delta >= 0.0 || u53 < exp(delta)) {
-            lat.t2r[p] = b;
-            lat.t2r[p + 1] = a;
-            lat.r2t[a] = p + 1;
-            lat.r2t[b] = p;
-            lat.acc[p] += 1;
+    const int R = lat.R, t = (int)threadIdx.x;
+    if (R <= kExchangeThreads) {
+        // inputs that do not depend on the energies, fetched first
+        const bool mine = t < R;
+        const int tc = mine ? t : 0;
+        // (global-typed loads: flat ones would also hold up the scalar waits)
+        const int32_t my_t2r = gptr(lat.t2r)[tc];
+        GAS const double *beta = gptr(lat.beta);
+        const double my_beta = beta[tc], my_beta1 = beta[min(tc + 1, R - 1)];
+        const bool pair = t + 1 < R && (t & 1) == (int)(k & 1);
+        const int pc = min(tc, max(R - 2, 0));
+        const uint64_t my_att = gptr(lat.att)[pc], my_acc = gptr(lat.acc)[pc];
+        double o[6];
+        GAS const double *orow = gptr(lat.obs) + 6 * (size_t)tc;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) o[q] = orow[q];
+        replica_totals(lat, nullptr, nullptr, nullptr, sE, sM);
+        if (mine) st2r[t] = my_t2r;
+        __syncthreads();
+        // pairs (p, p+1) with p = k mod 2: thread p decides its pair; the
+        // pairs are disjoint, so every slot is written by at most one thread
+        if (pair) {
+            const int a = st2r[t], b = st2r[t + 1];
+            const double delta = (my_beta1 - my_beta) * (sE[b] - sE[a]);
+            lat.att[t] = my_att + 1;
+            if (exchange_accept(lat, t, k, delta)) {
+                lat.acc[t] = my_acc + 1;
+                st2r[t] = b;
+                st2r[t + 1] = a;
+                lat.t2r[t] = b;
+                lat.t2r[t + 1] = a;
+                lat.r2t[a] = t + 1;
+                lat.r2t[b] = t;
+            }
         }
-    }
-    __syncthreads();
-    // one measurement per exchange step (Sec. 7), by temperature slot
-    for (int t = threadIdx.x; t < lat.R; t += kExchangeThreads) {
-        const int a = lat.t2r[t];
-        const double e = lat.E[a], m = lat.Mr[a], m2 = m * m;
-        double *o = lat.obs + 6 * (size_t)t;
-        o[0] += 1.0;
-        o[1] += e;
-        o[2] += e * e;
-        o[3] += fabs(m);
-        o[4] += m2;
-        o[5] += m2 * m2;
+        __syncthreads();
+        // one measurement per exchange step (Sec. 7), by temperature slot
+        if (mine) {
+            const int a = st2r[t];
+            const double e = sE[a], m = sM[a], m2 = m * m;
+            double *op = lat.obs + 6 * (size_t)t;
+            op[0] = o[0] + 1.0;
+            op[1] = o[1] + e;
+            op[2] = o[2] + e * e;
+            op[3] = o[3] + fabs(m);
+            op[4] = o[4] + m2;
+            op[5] = o[5] + m2 * m2;
+        }
+    } else {
+        replica_totals(lat);
+        __syncthreads();
+        for (int p = (int)(k & 1) + 2 * t; p + 1 < R; p += 2 * kExchangeThreads) {
+            const int a = lat.t2r[p], b = lat.t2r[p + 1];
+            const double delta = (lat.beta[p + 1] - lat.beta[p]) * (lat.E[b] - lat.E[a]);
+            lat.att[p] += 1;
+            if (exchange_accept(lat, p, k, delta)) {
+                lat.t2r[p] = b;
+                lat.t2r[p + 1] = a;
+                lat.r2t[a] = p + 1;
+                lat.r2t[b] = p;
+                lat.acc[p] += 1;
+            }
+        }
+        __syncthreads();
+        for (int q = t; q < R; q += kExchangeThreads) {
+            const int a = lat.t2r[q];
+            const double e = lat.E[a], m = lat.Mr[a], m2 = m * m;
+            double *o = lat.obs + 6 * (size_t)q;
+            o[0] += 1.0;
+            o[1] += e;
+            o[2] += e * e;
+            o[3] += fabs(m);
+            o[4] += m2;
+            o[5] += m2 * m2;
+        }
     }
     if (threadIdx.x == 0) {
         lat.ctrs[0] += (uint64_t)tadv;

@@ -235,6 +235,50 @@ def test_two_stream_split_matches_oracle(rfim_mod, oracle_mod, shape):
     g.close()
 
 
+def _oracle_calls(o, calls, R, want):
+    """Run the oracle through the same sweep calls, adding the per-slot
+    observable sums after every exchange step."""
+    for n, every in calls:
+        t = o.counters()[0]
+        while n > 0:
+            to_next = every - t % every
+            m = min(n, to_next)
+            o.sweep(m, every)
+            t += m
+            n -= m
+            if m == to_next:
+                E = o.energies()
+                M = o.magnetizations().astype(np.float64)
+                want += np.stack([np.ones(R), E, E * E, np.abs(M), M * M, M ** 4], axis=1)
+
+
+def test_split_streams_ragged_calls_match_oracle(rfim_mod, oracle_mod):
+    """Half-sweeps split over two streams that join at every exchange step:
+    the oracle's chain and observable sums, bit for bit, over calls that end
+    inside an interval, exchanges every 3 and every sweep, odd R (halves of 4
+    and 5), and a stretch with the Fourier measurement on."""
+    L, R = 32, 9
+    f = W.bimodal_fields(L, [49, L])
+    T = W.linear_temps(R, 1.0, 5.0)
+    g, o = make_pair(rfim_mod, oracle_mod, L, R, 1.0, 1.5, f, T, seed=31)
+    g.set_concurrency(2)
+    want = np.zeros((R, 6))
+    calls = [(7, 3), (5, 3), (4, 3), (8, 3), (5, 1), (2, 1)]
+    for n, every in calls:
+        g.sweep(n, every)
+    _oracle_calls(o, calls, R, want)
+    assert_same_state(g, o, "split streams, ragged calls")
+    assert np.array_equal(g.observables(), want)
+    g.set_measure(rfim_mod.MEASURE_FOURIER)
+    g.sweep(7, 3)
+    g.set_measure(0)
+    g.sweep(6, 2)
+    _oracle_calls(o, [(7, 3), (6, 2)], R, want)
+    assert_same_state(g, o, "split streams after a measured stretch")
+    assert np.array_equal(g.observables(), want)
+    g.close()
+
+
 def test_forced_split_small_lattice(rfim_mod, oracle_mod):
     """Two streams forced on a small streaming lattice (odd R: halves of 3
     and 4 replicas): still the oracle's chain; invalid stream counts are
