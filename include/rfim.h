@@ -211,6 +211,8 @@ int rfim_fourier(rfim_t *h, double *fourier);
  * per workgroup; mode 1 (L <= 32, nw <= 4)
  * keeps each replica in one workgroup's LDS (wg in {64, ..., 1024}) for all
  * sweeps of an exchange interval.  Other L have the single shape (0, 0, 0).
+ * A new handle starts from a shape chosen by L from measurements on gfx950
+ * (rfim_get_launch_shape reports it).
  * RFIM_EINVAL for a shape not valid for the handle's L. */
 int rfim_set_launch_shape(rfim_t *h, int mode, int nw, int wg);
 int rfim_get_launch_shape(const rfim_t *h, int *mode, int *nw, int *wg);

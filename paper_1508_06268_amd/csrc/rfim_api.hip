@@ -421,26 +421,30 @@ int compute_components(rfim *h) {
     return RFIM_OK;
 }
 
-// Default launch shape: tiny lattices run LDS-resident (launch-bound
-// otherwise), larger ones stream with four dwords per thread.  The
-// autotuner in the Python package measures and overrides these.
+// Default launch shape: lattices up to L = 32 run LDS-resident (streaming
+// is launch-bound there), larger ones stream with four dwords per thread.
+// The autotuner in the Python package measures and overrides these.
 void default_shape(int L, int R, int *mode, int *nw, int *wg) {
     if (!(L >= 8 && (L & (L - 1)) == 0)) {
         *mode = 0; *nw = 0; *wg = 0;
         return;
     }
-    if (L <= 16) {
+    // L <= 32: the LDS-resident shape, one replica per workgroup with one
+    // chunk per thread per half-sweep (a whole exchange interval per
+    // launch).  Measured on gfx950 at L = 32 against the best streaming
+    // shape: +36-42 % (continuous fields, R = 64), +70 % (+-1 fields, R = 32);
+    // streaming at L = 32 is launch-bound up to R ~ 128.
+    if (L <= 32) {
         *mode = 1;
-        *nw = L == 8 ? 1 : 2;
-        *wg = L == 8 ? 64 : 256;
+        *nw = L == 8 ? 1 : (L == 16 ? 2 : 4);
+        *wg = L == 8 ? 64 : (L == 16 ? 256 : 1024);
         return;
     }
-    // measured on gfx950: 4 dwords in 128-thread groups at L >= 64 (whole
-    // rows of 8 dwords are no faster); one dword per thread in 256-thread
-    // groups at L = 32
+    // L >= 64: streaming, 4 dwords in 128-thread groups (whole rows of 8
+    // dwords are no faster)
     *mode = 0;
-    *nw = L >= 64 ? 4 : 1;
-    *wg = L >= 64 ? 128 : 256;
+    *nw = 4;
+    *wg = 128;
     (void)R;
 }
 

@@ -261,6 +261,7 @@ def test_split_streams_ragged_calls_match_oracle(rfim_mod, oracle_mod):
     f = W.bimodal_fields(L, [49, L])
     T = W.linear_temps(R, 1.0, 5.0)
     g, o = make_pair(rfim_mod, oracle_mod, L, R, 1.0, 1.5, f, T, seed=31)
+    g.set_launch_shape(0, 1, 256)      # streaming (the split applies to streaming shapes)
     g.set_concurrency(2)
     want = np.zeros((R, 6))
     calls = [(7, 3), (5, 3), (4, 3), (8, 3), (5, 1), (2, 1)]
@@ -287,6 +288,7 @@ def test_forced_split_small_lattice(rfim_mod, oracle_mod):
     f = W.bimodal_fields(L, [23, L])
     T = W.linear_temps(R, 1.0, 5.0)
     g, o = make_pair(rfim_mod, oracle_mod, L, R, 1.0, 1.5, f, T, seed=5)
+    g.set_launch_shape(0, 1, 256)      # streaming (the split applies to streaming shapes)
     g.set_concurrency(2)
     assert g.concurrency() == 2
     g.sweep(17, 4)
