@@ -100,8 +100,10 @@ typedef struct rfim_params {
  * handle's stream(s), or NULL (the call then fails with RFIM_ENOMEM);
  * free(ptr, ctx) takes back a pointer alloc returned, after the handle's
  * work on it has finished.  Both run on the thread that called into the
- * library (create, rfim_set_measure, destroy).  A caching allocator (e.g.
- * PyTorch's) can serve them. */
+ * library (create, rfim_set_measure, destroy).  A handle asks for one block
+ * at create time (all its buffers) and three more when rfim_set_measure
+ * first turns the measurement on.  A caching allocator (e.g. PyTorch's) can
+ * serve them. */
 typedef struct rfim_alloc {
     void *(*alloc)(size_t bytes, void *ctx);
     void (*free)(void *ptr, void *ctx);

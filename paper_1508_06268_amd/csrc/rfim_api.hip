@@ -67,7 +67,9 @@ struct rfim {
     int measure = 0;
     int32_t *d_fpart = nullptr;
     double *d_trig = nullptr, *d_fobs = nullptr;
-    // device memory
+    // device memory: one allocation (d_arena, see arena_layout) carved into
+    // the buffers below; the measurement buffers are allocated on demand
+    void *d_arena = nullptr;
     uint8_t *d_spins = nullptr, *d_fbits = nullptr;
     float *d_fhf = nullptr, *d_fraw = nullptr, *d_betaf = nullptr;
     uint32_t *d_thr = nullptr;
@@ -152,14 +154,7 @@ void dev_free(rfim *h, void *p) {
 }
 
 void free_device(rfim *h) {
-    void *ptrs[] = {h->d_spins, h->d_fbits, h->d_fhf, h->d_fraw, h->d_betaf, h->d_thr,
-                    h->d_beta,  h->d_part,  h->d_E,   h->d_t2r,  h->d_r2t,   h->d_att,
-                    h->d_acc,   h->d_ctrs,  h->d_B,   h->d_M,    h->d_F,     h->d_Mr,
-                    h->d_obs};
-    for (void *p : ptrs) dev_free(h, p);
-    dev_free(h, h->d_lat);
-    dev_free(h, h->d_smap);
-    dev_free(h, h->d_rmap);
+    dev_free(h, h->d_arena);
     dev_free(h, h->d_fpart);
     dev_free(h, h->d_trig);
     dev_free(h, h->d_fobs);
@@ -263,57 +258,93 @@ void for_each_site(int L, F f) {
     }
 }
 
+// A handle's device buffers live in one allocation, in this order, each
+// piece on a 256-byte boundary (byte offsets; absent pieces have size 0).
+struct ArenaLayout {
+    size_t spins, fbits, fhf, fraw, thr, betaf, beta, t2r, r2t, att, acc, ctrs, part, E, Mr, obs, B, M, F,
+        lat, rmap, smap, total;
+    size_t smap_cap;   // streaming workgroup-map entries (0 for other L)
+};
+
+ArenaLayout arena_layout(int L, int R_cap, int kind) {
+    const size_t N = (size_t)L * L * L, Rc = (size_t)R_cap;
+    const bool pow2 = L >= 8 && (L & (L - 1)) == 0;
+    // partials sized for the shape with the most workgroups per replica,
+    // maps for the streaming shape with the most workgroups per replica
+    size_t maxblk = 64, maxw = 1;
+    if (pow2)
+        for (int nw : {1, 2, 4, 8})
+            for (int wg : {64, 128, 256})
+                if (rfim_dev::shape_valid(L, 0, nw, wg)) {
+                    maxblk = std::max(maxblk, (size_t)rfim_dev::blocks_per_replica(L, 0, nw, wg));
+                    maxw = std::max(maxw, (size_t)rfim_dev::stream_blocks_per_replica(L, nw, wg));
+                }
+    ArenaLayout a{};
+    size_t off = 0;
+    auto take = [&off](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    a.spins = take(Rc * N);
+    a.fbits = take(kind == 0 ? N : 0);
+    a.fhf = take(kind == 0 ? 0 : N * sizeof(float));
+    a.fraw = take(kind == 0 ? 0 : N * sizeof(float));
+    a.thr = take(Rc * 32 * sizeof(uint32_t));
+    a.betaf = take(Rc * sizeof(float));
+    a.beta = take(Rc * sizeof(double));
+    a.t2r = take(Rc * sizeof(int32_t));
+    a.r2t = take(Rc * sizeof(int32_t));
+    a.att = take(Rc * sizeof(uint64_t));
+    a.acc = take(Rc * sizeof(uint64_t));
+    a.ctrs = take(2 * sizeof(uint64_t));
+    a.part = take(Rc * maxblk * 3 * sizeof(double));
+    a.E = take(Rc * sizeof(double));
+    a.Mr = take(Rc * sizeof(double));
+    a.obs = take(Rc * 6 * sizeof(double));
+    a.B = take(Rc * sizeof(int64_t));
+    a.M = take(Rc * sizeof(int64_t));
+    a.F = take(Rc * sizeof(double));
+    a.lat = take(sizeof(Lattice));
+    a.rmap = take(Rc * sizeof(uint2));
+    a.smap_cap = pow2 ? Rc * maxw : 0;
+    a.smap = take(a.smap_cap * sizeof(uint2));
+    a.total = off;
+    return a;
+}
+
 int alloc_device(rfim *h) {
-    const size_t N = (size_t)h->N, half = N / 2, Rc = (size_t)h->R_cap;
-    // partials buffer sized for the shape with the most workgroups
-    int maxblk = 64;
-    if (h->log2L >= 3) {
-        for (int nw : {1, 2, 4, 8})
-            for (int wg : {64, 128, 256})
-                if (rfim_dev::shape_valid(h->L, 0, nw, wg))
-                    maxblk = std::max(maxblk, rfim_dev::blocks_per_replica(h->L, 0, nw, wg));
-    }
     h->nblk = rfim_dev::blocks_per_replica(h->L, h->mode, h->nw, h->wg);
-#define ALLOC(ptr, bytes)                                                                \
-    do {                                                                                 \
-        int rc_ = dev_alloc(h, (void **)&(ptr), (bytes));                                \
-        if (rc_) return rc_;                                                             \
-    } while (0)
-    ALLOC(h->d_spins, Rc * N);
+    const ArenaLayout a = arena_layout(h->L, h->R_cap, h->kind);
+    int rc;
+    if ((rc = dev_alloc(h, &h->d_arena, a.total))) return rc;
+    char *b = (char *)h->d_arena;
+    h->d_spins = (uint8_t *)(b + a.spins);
     if (h->kind == 0) {
-        ALLOC(h->d_fbits, N);
+        h->d_fbits = (uint8_t *)(b + a.fbits);
     } else {
-        ALLOC(h->d_fhf, N * sizeof(float));
-        ALLOC(h->d_fraw, N * sizeof(float));
+        h->d_fhf = (float *)(b + a.fhf);
+        h->d_fraw = (float *)(b + a.fraw);
     }
-    ALLOC(h->d_thr, Rc * 32 * sizeof(uint32_t));
-    ALLOC(h->d_betaf, Rc * sizeof(float));
-    ALLOC(h->d_beta, Rc * sizeof(double));
-    ALLOC(h->d_t2r, Rc * sizeof(int32_t));
-    ALLOC(h->d_r2t, Rc * sizeof(int32_t));
-    ALLOC(h->d_att, Rc * sizeof(uint64_t));
-    ALLOC(h->d_acc, Rc * sizeof(uint64_t));
-    ALLOC(h->d_ctrs, 2 * sizeof(uint64_t));
-    ALLOC(h->d_part, Rc * (size_t)maxblk * 3 * sizeof(double));
-    ALLOC(h->d_E, Rc * sizeof(double));
-    ALLOC(h->d_Mr, Rc * sizeof(double));
-    ALLOC(h->d_obs, Rc * 6 * sizeof(double));
-    ALLOC(h->d_B, Rc * sizeof(int64_t));
-    ALLOC(h->d_M, Rc * sizeof(int64_t));
-    ALLOC(h->d_F, Rc * sizeof(double));
-    ALLOC(h->d_lat, sizeof(Lattice));
-    ALLOC(h->d_rmap, Rc * sizeof(uint2));
-    if (h->log2L >= 3) {
-        size_t maxw = 1;
-        for (int nw : {1, 2, 4, 8})
-            for (int wg : {64, 128, 256})
-                if (rfim_dev::shape_valid(h->L, 0, nw, wg))
-                    maxw = std::max(maxw, (size_t)rfim_dev::stream_blocks_per_replica(h->L, nw, wg));
-        h->smap_cap = Rc * maxw;
-        ALLOC(h->d_smap, h->smap_cap * sizeof(uint2));
-    }
-#undef ALLOC
-    (void)half;
+    h->d_thr = (uint32_t *)(b + a.thr);
+    h->d_betaf = (float *)(b + a.betaf);
+    h->d_beta = (double *)(b + a.beta);
+    h->d_t2r = (int32_t *)(b + a.t2r);
+    h->d_r2t = (int32_t *)(b + a.r2t);
+    h->d_att = (uint64_t *)(b + a.att);
+    h->d_acc = (uint64_t *)(b + a.acc);
+    h->d_ctrs = (uint64_t *)(b + a.ctrs);
+    h->d_part = (double *)(b + a.part);
+    h->d_E = (double *)(b + a.E);
+    h->d_Mr = (double *)(b + a.Mr);
+    h->d_obs = (double *)(b + a.obs);
+    h->d_B = (int64_t *)(b + a.B);
+    h->d_M = (int64_t *)(b + a.M);
+    h->d_F = (double *)(b + a.F);
+    h->d_lat = (Lattice *)(b + a.lat);
+    h->d_rmap = (uint2 *)(b + a.rmap);
+    h->smap_cap = a.smap_cap;
+    h->d_smap = a.smap_cap ? (uint2 *)(b + a.smap) : nullptr;
     return RFIM_OK;
 }
 
@@ -1502,22 +1533,7 @@ struct rfim_pool {
 namespace {
 
 // Device bytes one realization reserves (what alloc_device allocates).
-size_t device_bytes(int L, int R_cap, int kind) {
-    const size_t N = (size_t)L * L * L, Rc = (size_t)R_cap;
-    size_t maxblk = 64, maxw = 1;
-    const bool pow2 = L >= 8 && (L & (L - 1)) == 0;
-    if (pow2)
-        for (int nw : {1, 2, 4, 8})
-            for (int wg : {64, 128, 256})
-                if (rfim_dev::shape_valid(L, 0, nw, wg)) {
-                    maxblk = std::max(maxblk, (size_t)rfim_dev::blocks_per_replica(L, 0, nw, wg));
-                    maxw = std::max(maxw, (size_t)rfim_dev::stream_blocks_per_replica(L, nw, wg));
-                }
-    size_t b = Rc * N + (kind == 0 ? N : 8 * N);
-    b += Rc * (32 * 4 + 4 + 8 + 4 + 4 + 8 + 8 + 8 + 8 + 8 + 8);   // tables, perms, stats, E/B/M/F
-    b += 16 + sizeof(Lattice) + Rc * maxblk * 24 + Rc * sizeof(uint2) + (pow2 ? Rc * maxw * sizeof(uint2) : 0);
-    return b;
-}
+size_t device_bytes(int L, int R_cap, int kind) { return arena_layout(L, R_cap, kind).total; }
 
 rfim_pool::Shape &pool_shape(rfim_pool *p, int L, int kind) {
     for (auto &s : p->shapes)
