@@ -376,3 +376,48 @@ def test_torch_allocator_serves_the_handle(rfim_mod, oracle_mod):
     g.close()
     torch.cuda.synchronize()
     assert torch.cuda.memory_allocated() == before
+
+
+@pytest.mark.parametrize("R", [1024, 1025, 1500])
+def test_many_replicas_match_oracle(rfim_mod, oracle_mod, R):
+    """The exchange step runs out of LDS up to 1024 replicas and through
+    global memory beyond (the energy totals then take several replica tiles):
+    both sides of the boundary give the oracle's chain and observable sums,
+    bit for bit."""
+    L = 8
+    f = W.bimodal_fields(L, [50, R])
+    T = W.linear_temps(R, 1.0, 6.0)
+    g, o = make_pair(rfim_mod, oracle_mod, L, R, 1.0, 1.0, f, T, seed=R)
+    calls = [(12, 5), (8, 5)]
+    want = np.zeros((R, 6))
+    for n, every in calls:
+        g.sweep(n, every)
+    _oracle_calls(o, calls, R, want)
+    assert_same_state(g, o, "R=%d" % R)
+    assert np.array_equal(g.observables(), want)
+    g.close()
+
+
+@pytest.mark.parametrize("kind", ["b", "g"])
+def test_single_replica_and_empty_calls(rfim_mod, oracle_mod, kind):
+    """Degenerate cases: one replica (exchange steps with no pair still
+    advance the counters and record the measurement) and calls of zero
+    sweeps (no change at all)."""
+    L, R = 8, 1
+    f = W.bimodal_fields(L, [51, 0]) if kind == "b" else W.gaussian_fields(L, [51, 0])
+    g, o = make_pair(rfim_mod, oracle_mod, L, R, 1.0, 1.5, f, [2.5], seed=3)
+    g.sweep(0, 10)
+    o.sweep(0, 10)
+    assert g.counters() == o.counters() == (0, 0)
+    g.sweep(25, 10)
+    o.sweep(25, 10)
+    if kind == "b":
+        assert_same_state(g, o, "R=1")
+    else:
+        assert g.counters() == o.counters()
+        assert np.array_equal(g.perm(), o.perm())
+    assert g.observables()[0, 0] == 2.0
+    before = (g.spins().copy(), g.counters())
+    g.sweep(0, 5)
+    assert np.array_equal(g.spins(), before[0]) and g.counters() == before[1]
+    g.close()
