@@ -421,3 +421,31 @@ def test_single_replica_and_empty_calls(rfim_mod, oracle_mod, kind):
     g.sweep(0, 5)
     assert np.array_equal(g.spins(), before[0]) and g.counters() == before[1]
     g.close()
+
+
+@pytest.mark.parametrize("L,R,shape", [(32, 513, (0, 1, 64)), (32, 40, (0, 1, 64)), (36, 40, None),
+                                       (16, 5, (0, 1, 64))])
+def test_energy_totals_over_block_ranges(rfim_mod, oracle_mod, L, R, shape):
+    """Per-replica totals over the workgroup partials with every range width:
+    64 blocks per replica and 513 replicas (one group, 8 batches of 8 loads),
+    64 blocks and 40 replicas (8 groups of 8), 23 generic blocks and 40
+    replicas (ranges of 3 and 2), 8 blocks and 5 replicas (ranges of 1).
+    Energies and components from random states equal the oracle's, and a
+    short run with exchanges at R = 513 follows the oracle's chain."""
+    f = W.bimodal_fields(L, [52, L])
+    T = W.linear_temps(R, 1.0, 5.0)
+    g, o = make_pair(rfim_mod, oracle_mod, L, R, 1.0, 1.25, f, T, seed=17)
+    if shape is not None:
+        g.set_launch_shape(*shape)
+    s = W.random_spins(R, L, [52, L, R])
+    g.set_spins(s)
+    o.set_spins(s)
+    gb, gf, gm = g.components()
+    ob, of, om = o.components()
+    assert np.array_equal(gb, ob) and np.array_equal(gf, of) and np.array_equal(gm, om)
+    assert np.array_equal(g.energies(), o.energies())
+    if R == 513:
+        g.sweep(4, 2)
+        o.sweep(4, 2)
+        assert_same_state(g, o, "L=%d R=%d shape %s" % (L, R, shape))
+    g.close()
