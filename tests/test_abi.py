@@ -68,3 +68,28 @@ def test_null_handle_getters_and_setters_fail_cleanly(rfim_mod):
     assert lib.rfim_set_measure(None, 1) == -1
     assert lib.rfim_fourier(None, None) == -1
     assert b"NULL" in lib.rfim_last_error()
+
+
+@pytest.mark.parametrize("L,R,R_cap,kind", [(8, 16, 0, "b"), (32, 64, 0, "g"), (64, 128, 192, "b"),
+                                            (64, 128, 192, "g"), (24, 5, 9, "b")])
+def test_pool_bytes_needed_accounts_every_buffer(rfim_mod, L, R, R_cap, kind):
+    """The device bytes a realization reserves (host arithmetic, no GPU):
+    at least its spins (R_cap L^3 bytes) and fields (L^3 bytes, or two FP32
+    copies for continuous fields), whole 256-byte pieces, growing with R_cap;
+    invalid parameters give 0."""
+    from paper_1508_06268_amd import workloads as W
+
+    f = W.bimodal_fields(L, [0, 1]) if kind == "b" else W.gaussian_fields(L, [0, 1])
+    Rc = R_cap or R
+    w = W.Realization(L=L, R=R, J=1.0, h=1.0, fields=f, temps=W.linear_temps(R, 1.0, 5.0), seed=0,
+                      sweeps=0, every=10, R_cap=R_cap)
+    need = rfim_mod.Pool.bytes_needed(w)
+    N = L ** 3
+    assert need >= Rc * N + (N if kind == "b" else 8 * N)
+    assert need % 256 == 0
+    bigger = W.Realization(L=L, R=R, J=1.0, h=1.0, fields=f, temps=W.linear_temps(R, 1.0, 5.0), seed=0,
+                           sweeps=0, every=10, R_cap=Rc + 8)
+    assert rfim_mod.Pool.bytes_needed(bigger) >= need + 8 * N
+    bad = W.Realization(L=L, R=R, J=1.0, h=1.0, fields=f, temps=W.linear_temps(R, 5.0, 1.0), seed=0,
+                        sweeps=0, every=10, R_cap=R_cap)
+    assert rfim_mod.Pool.bytes_needed(bad) == 0
