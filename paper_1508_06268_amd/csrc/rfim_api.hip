@@ -578,6 +578,20 @@ int sweep_impl(rfim *h, int64_t n, int every) {
         lb.r0 = ra;
         lb.nblocks = (h->R - ra) * wpr;
     }
+    // Two streams: one fork at the start of the call and one join at its
+    // end.  At each exchange step the streams meet once: the stream running
+    // the step waits for the other's last half-sweep, runs the step (and the
+    // measurement), and the other waits for it.  The step alternates between
+    // the streams: whichever stream ran the previous step went on at once
+    // while the other waited for it, so the other reaches the next step
+    // later, and running the step there makes its own wait free -- one event
+    // latency per interval on the critical path instead of two.  The first
+    // step of a call runs on the second stream, which the fork delays.
+    bool step_on_aux = true;
+    if (split) {
+        HIPCHK(hipEventRecord(h->ev_fork, h->stream));
+        HIPCHK(hipStreamWaitEvent(h->aux, h->ev_fork, 0));
+    }
     int64_t remaining = n;
     while (remaining > 0) {
         int64_t to_next = every > 0 ? (int64_t)(every - (int64_t)(h->t % (uint64_t)every)) : remaining;
@@ -587,8 +601,6 @@ int sweep_impl(rfim *h, int64_t n, int every) {
         if (pow2 && h->mode == 1) {
             HIPCHK(rfim_dev::launch_resident(ln, m, fused ? 1 : 0, h->stream));
         } else if (pow2 && split) {
-            HIPCHK(hipEventRecord(h->ev_fork, h->stream));
-            HIPCHK(hipStreamWaitEvent(h->aux, h->ev_fork, 0));
             for (int q = 0; q < m; ++q) {
                 const int e = fused && q == m - 1;
                 HIPCHK(rfim_dev::launch_stream_sweep(la, 0, q, 0, h->stream));
@@ -596,8 +608,6 @@ int sweep_impl(rfim *h, int64_t n, int every) {
                 HIPCHK(rfim_dev::launch_stream_sweep(la, 1, q, e, h->stream));
                 HIPCHK(rfim_dev::launch_stream_sweep(lb, 1, q, e, h->aux));
             }
-            HIPCHK(hipEventRecord(h->ev_join, h->aux));
-            HIPCHK(hipStreamWaitEvent(h->stream, h->ev_join, 0));
         } else if (pow2) {
             for (int q = 0; q < m; ++q) {
                 HIPCHK(rfim_dev::launch_stream_sweep(ln, 0, q, 0, h->stream));
@@ -610,16 +620,39 @@ int sweep_impl(rfim *h, int64_t n, int every) {
             }
         }
         if (exch) {
-            if (!fused) HIPCHK(rfim_dev::launch_energy(lat, h->stream));
-            HIPCHK(rfim_dev::launch_exchange(h->d_lat, 1, m, h->stream));
+            hipStream_t xs = h->stream;
+            if (split) {
+                xs = step_on_aux ? h->aux : h->stream;
+                hipStream_t other = step_on_aux ? h->stream : h->aux;
+                HIPCHK(hipEventRecord(h->ev_join, other));
+                HIPCHK(hipStreamWaitEvent(xs, h->ev_join, 0));
+            }
+            if (!fused) HIPCHK(rfim_dev::launch_energy(lat, xs));
+            HIPCHK(rfim_dev::launch_exchange(h->d_lat, 1, m, xs));
             int rc;
-            if ((rc = measure_after_exchange(h, h->stream))) return rc;
+            if ((rc = measure_after_exchange(h, xs))) return rc;
+            if (split) {
+                hipStream_t other = step_on_aux ? h->stream : h->aux;
+                HIPCHK(hipEventRecord(h->ev_fork, xs));
+                HIPCHK(hipStreamWaitEvent(other, h->ev_fork, 0));
+                step_on_aux = !step_on_aux;
+            }
             h->k += 1;
         } else {
+            // the counter advance changes the sweep index both streams read:
+            // join first (this is the last interval of the call)
+            if (split) {
+                HIPCHK(hipEventRecord(h->ev_join, h->aux));
+                HIPCHK(hipStreamWaitEvent(h->stream, h->ev_join, 0));
+            }
             HIPCHK(rfim_dev::launch_advance(lat, m, h->stream));
         }
         h->t += (uint64_t)m;
         remaining -= m;
+    }
+    if (split) {
+        HIPCHK(hipEventRecord(h->ev_join, h->aux));
+        HIPCHK(hipStreamWaitEvent(h->stream, h->ev_join, 0));
     }
     return RFIM_OK;
 }
