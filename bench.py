@@ -390,13 +390,15 @@ def main():
 
     # Roofline leg: the dominant kernel (one half-sweep of every replica) at
     # the production shape, timed with events on the handle's stream.
-    # One launch covers every replica (one stream); the production path
-    # splits large half-sweeps over two streams, timed here as well.
-    # Median of 10 repetitions of 40 sweeps (80 half-sweeps) each.
+    # One launch covers every replica (one stream): median of 10 repetitions
+    # of 40 sweeps (80 launches) each.  The production path splits large
+    # half-sweeps over two streams, timed here as well in its steady state:
+    # median of 10 repetitions of 200 sweeps, so that the fork and join of
+    # each call weigh little.
     h = handles[-1]
-    n_roof, reps = 40, 10
+    reps = 10
 
-    def half_sweep_us(streams):
+    def half_sweep_us(streams, n_roof):
         h.set_concurrency(streams)
         h.sweep(10, 0)
         stream.synchronize()
@@ -411,8 +413,8 @@ def main():
             times.append(e0.elapsed_time(e1) * 1e3 / (2 * n_roof))
         return float(np.median(times))
 
-    launch_us = half_sweep_us(1)
-    split_us = half_sweep_us(2)
+    launch_us = half_sweep_us(1, 40)
+    split_us = half_sweep_us(2, 200)
     h.set_concurrency(0)
     mode, nw, wg = h.launch_shape()
     kind = h.field_kind
