@@ -36,10 +36,11 @@
  * A handle owns its device memory (from hipMalloc, or from a provider given
  * to rfim_create_ex) and orders all its work on one HIP stream (its own, or
  * one set with rfim_set_stream); inside large streaming sweeps it forks half
- * of the replicas onto a second stream of its own and joins it back before
- * the exchange step (rfim_set_concurrency), so callers see one stream.  One
- * handle is used from one thread at a time; different handles are
- * independent.
+ * of the replicas onto a second stream and joins it back before the exchange
+ * step (rfim_set_concurrency), so callers see one stream.  That second
+ * stream belongs to the library, one per (device, handle stream), shared by
+ * the handles issuing on that stream.  One handle is used from one thread at
+ * a time; different handles are independent.
  *
  * Errors.  Calls return RFIM_OK (0) or a negative status; constructors
  * return NULL.  rfim_last_error() gives a thread-local message for the last
@@ -222,8 +223,9 @@ int rfim_get_launch_shape(const rfim_t *h, int *mode, int *nw, int *wg);
 /* Streams a streaming-mode half-sweep runs on (no effect on results).
  * Replicas do not interact between exchange steps, so the library can run
  * the half-sweeps of replicas [0, R/2) on the handle stream and those of
- * [R/2, R) on a second stream it owns, forked from and joined back into the
- * handle stream by events around every exchange interval; the two launch
+ * [R/2, R) on a second stream (the library's, one per device and handle
+ * stream, on a hardware queue of its own), forked from and joined back into
+ * the handle stream by events around every exchange interval; the two launch
  * sequences then fill each other's start-up and drain time.  streams = 0:
  * automatic (two streams when each half holds at least 2^22 sites of one
  * colour), 1: always one stream, 2: two streams whenever R >= 2.  Only
@@ -291,19 +293,78 @@ void rfim_pool_destroy(rfim_pool_t *p);
  * parameters are invalid). */
 size_t rfim_pool_bytes_needed(const rfim_params_t *params);
 /* Admit: a slot id >= 0, RFIM_EBUSY if the budget cannot hold it now (try
- * again after a release), or another negative status. */
+ * again after a release), or another negative status.  The slot has no
+ * schedule: the caller advances it with rfim_pool_step, runs its insertion
+ * steps with rfim_pool_adapt and decides when it is done. */
 int rfim_pool_admit(rfim_pool_t *p, const rfim_params_t *params);
-/* Every active slot advances `quantum` sweeps (a multiple of
- * exchange_every; every slot must be at an exchange boundary).  Async. */
+
+/* A realization request with the adaptive schedule of Sec. 4 and the
+ * realization-level parallelism of Sec. 8: `trials` trial runs of
+ * sweeps_per_trial sweeps, each followed by one insertion step (rates below
+ * rate_threshold, at most max_insert_per_trial new temperatures, R bounded
+ * by params.R_cap; see rfim_adapt_temps), then production_sweeps sweeps.
+ * The exchange interval is the one rfim_pool_step is called with. */
+typedef struct rfim_job {
+    rfim_params_t params;
+    int trials;                 /* >= 0 */
+    int64_t sweeps_per_trial;   /* >= 1 when trials > 0 */
+    double rate_threshold;
+    int max_insert_per_trial;   /* >= 0 */
+    int64_t production_sweeps;  /* >= 1 */
+} rfim_job_t;
+/* Admit a job: as rfim_pool_admit, but the pool runs the schedule itself:
+ * every rfim_pool_step advances the slot, runs its insertion step when a
+ * trial run ends, and marks it finished when its production sweeps are
+ * done; a finished slot is no longer stepped and is reported by
+ * rfim_pool_poll until released.  RFIM_EINVAL for a schedule with a
+ * negative count, an empty trial run or no production sweeps, RFIM_ECAP
+ * if its sweeps pass 2^31 - 1. */
+int rfim_pool_admit_job(rfim_pool_t *p, const rfim_job_t *job);
+
+/* Every slot that is admitted and not finished advances `quantum` sweeps
+ * (a multiple of exchange_every; every slot must be at an exchange
+ * boundary; for a job, its next schedule boundary must lie a multiple of
+ * `quantum` sweeps ahead, else RFIM_EINVAL before any work).  Asynchronous,
+ * except that it synchronizes when a job's trial run ends (the insertion
+ * step reads the exchange counters). */
 int rfim_pool_step(rfim_pool_t *p, int quantum, int exchange_every);
+
+/* Finished jobs not yet released: writes up to `max` slot ids (ascending)
+ * into done[] and returns how many it wrote; with max = 0 (done may be
+ * NULL) returns how many there are.  Host-side state only; no device
+ * work. */
+int rfim_pool_poll(rfim_pool_t *p, int *done, int max);
+
+/* The state of a slot (finished or not).  The caller sets `capacity` and
+ * the array pointers (each may be NULL to skip it); the library fills R,
+ * the arrays by temperature slot (ascending T), the slot's sweep and
+ * exchange counters, the spin-flip attempts issued for it and whether its
+ * schedule is complete.  RFIM_ECAP if an array is given and capacity < R
+ * (R is still written).  Synchronizes. */
+typedef struct rfim_result {
+    int R;                      /* out */
+    int capacity;               /* in: entries each non-NULL array holds */
+    double *temps;              /* out [R] */
+    double *energies;           /* out [R], E of the replica at each slot */
+    int64_t *magnetizations;    /* out [R] */
+    int32_t *perm;              /* out [R], slot -> replica id */
+    uint64_t sweeps, exchanges; /* out: counters t and k of the slot */
+    uint64_t attempts;          /* out: R * L^3 per sweep, summed */
+    int finished;               /* out: 1 once its schedule is complete */
+} rfim_result_t;
+int rfim_pool_result(rfim_pool_t *p, int slot, rfim_result_t *res);
+
 /* One adaptive insertion step (Sec. 4) for a slot from the exchange
  * counters it accumulated since its last reset (admission or previous
- * step); see rfim_adapt_temps.  Synchronizes; returns the new R. */
+ * step); see rfim_adapt_temps.  Synchronizes; returns the new R.
+ * RFIM_ESTATE for a job's slot (the pool runs its insertions). */
 int rfim_pool_adapt(rfim_pool_t *p, int slot, double rate_threshold, int max_insert, int R_cap);
+/* Release a slot (finished or not) and its device memory.  Synchronizes. */
 int rfim_pool_release(rfim_pool_t *p, int slot);
 /* Borrowed handle of a slot for observables and state (see
  * rfim_batch_item). */
 rfim_t *rfim_pool_item(rfim_pool_t *p, int slot);
+/* Slots admitted and not released (finished jobs included). */
 int rfim_pool_active(const rfim_pool_t *p);
 size_t rfim_pool_reserved(const rfim_pool_t *p);
 int rfim_pool_set_shape(rfim_pool_t *p, int L, int field_kind, int mode, int nw, int wg);

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <queue>
 #include <string>
@@ -43,6 +44,72 @@ int fail(int code, const char *fmt, ...) {
 constexpr int kMaxR = 65536;
 constexpr uint64_t kMaxSweeps = 0x7FFFFFFFull;
 
+// A stream for concurrent lanes of work.  It is created with a CU mask that
+// enables every CU of the device: the runtime gives such a stream a hardware
+// queue of its own instead of one shared round-robin from its pool of
+// GPU_MAX_HW_QUEUES queues, so two lanes cannot end up serialized on one
+// queue by the order in which the process happened to create its streams.
+// Falls back to an ordinary non-blocking stream.
+hipError_t create_lane_stream(hipStream_t *s) {
+    *s = nullptr;
+    int dev = 0, ncu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess && ncu > 0) {
+        std::vector<uint32_t> mask((size_t)(ncu + 31) / 32, 0u);
+        for (int c = 0; c < ncu; ++c) mask[(size_t)c >> 5] |= 1u << (c & 31);
+        e = hipExtStreamCreateWithCUMask(s, (uint32_t)mask.size(), mask.data());
+        if (e == hipSuccess) return e;
+    }
+    (void)hipGetLastError();
+    return hipStreamCreateWithFlags(s, hipStreamNonBlocking);
+}
+
+// The second stream of the two-stream sweeps, one per (device, handle
+// stream) and shared by every handle issuing on that stream, reference
+// counted.  Each call forks from and joins back into its handle stream, so
+// handles sharing a stream also share its order on the second stream.
+struct SideStream {
+    hipStream_t main;
+    int device;
+    hipStream_t side;
+    int refs;
+};
+std::mutex g_side_mu;
+std::vector<SideStream> g_side;
+
+hipError_t acquire_side_stream(hipStream_t main, hipStream_t *side) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(g_side_mu);
+    for (auto &s : g_side)
+        if (s.main == main && s.device == dev) {
+            ++s.refs;
+            *side = s.side;
+            return hipSuccess;
+        }
+    hipStream_t q = nullptr;
+    if ((e = create_lane_stream(&q)) != hipSuccess) return e;
+    g_side.push_back({main, dev, q, 1});
+    *side = q;
+    return hipSuccess;
+}
+
+void release_side_stream(hipStream_t side) {
+    if (!side) return;
+    std::lock_guard<std::mutex> lock(g_side_mu);
+    for (size_t i = 0; i < g_side.size(); ++i)
+        if (g_side[i].side == side) {
+            if (--g_side[i].refs == 0) {
+                (void)hipStreamSynchronize(side);
+                (void)hipStreamDestroy(side);
+                g_side.erase(g_side.begin() + (long)i);
+            }
+            return;
+        }
+}
+
 }  // namespace
 
 struct rfim {
@@ -55,11 +122,14 @@ struct rfim {
     std::vector<double> T;          // by slot
     // host mirrors of the device counters
     uint64_t t = 0, k = 0;
-    // stream; a second internal stream takes half of the replicas of large
-    // streaming sweeps (fork and join through events on the handle stream)
+    // stream; a second stream takes half of the replicas of large streaming
+    // sweeps (fork and join through events on the handle stream).  The
+    // second stream is shared by every handle that issues on the same
+    // stream (see acquire_side_stream).
     hipStream_t stream = nullptr;
     bool own_stream = false;
     hipStream_t aux = nullptr;
+    hipStream_t aux_for = nullptr;  // the handle stream `aux` was acquired for
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int concurrency = 0;            // see rfim_set_concurrency
     rfim_alloc_t alloc = {nullptr, nullptr, nullptr};   // device memory provider (rfim_create_ex)
@@ -160,7 +230,9 @@ void free_device(rfim *h) {
     dev_free(h, h->d_fobs);
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);
-    if (h->aux) (void)hipStreamDestroy(h->aux);
+    release_side_stream(h->aux);
+    h->aux = nullptr;
+    h->aux_for = nullptr;
 }
 
 int validate(const rfim_params_t *p, int *kind_out) {
@@ -553,10 +625,15 @@ void destroy_impl(rfim *h) {
 constexpr long long kSplitMinAttempts = 1ll << 22;
 
 int ensure_aux(rfim *h) {
-    if (h->aux) return RFIM_OK;
-    HIPCHK(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
-    HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+    if (h->aux && h->aux_for == h->stream) return RFIM_OK;
+    if (h->aux) {                   // the handle stream changed since
+        release_side_stream(h->aux);
+        h->aux = nullptr;
+    }
+    HIPCHK(acquire_side_stream(h->stream, &h->aux));
+    h->aux_for = h->stream;
+    if (!h->ev_fork) HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+    if (!h->ev_join) HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
     return RFIM_OK;
 }
 
@@ -1281,14 +1358,24 @@ constexpr int kMaxSideStreams = 3;
 struct Lane {
     rfim_dev::Launch ln;
     long long work;
+    bool fused;         // the class's sweep kernels write the energy partials
 };
+
+// True when the sweep kernels of class c write its items' energy partials
+// (resident shapes, and streaming shapes with at most kMaxFusedBlocks
+// workgroups per replica); other classes get the separate energy kernel
+// before the exchange step.
+bool class_fused(const rfim_batch *b, const rfim_batch::Class &c) {
+    if (c.members.empty()) return true;
+    return rfim_dev::fused_energy(b->items[c.members[0]]->lattice());
+}
 
 int ensure_side_streams(rfim_batch *b, int n) {
     if (!b->ev_fork) HIPCHK(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
     while ((int)b->aux.size() < n) {
         hipStream_t q = nullptr;
         hipEvent_t e = nullptr;
-        HIPCHK(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+        HIPCHK(create_lane_stream(&q));
         b->aux.push_back(q);
         HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         b->ev_join.push_back(e);
@@ -1301,6 +1388,7 @@ int batch_segment(rfim_batch *b, int m, bool exch) {
     std::vector<Lane> lanes;
     for (const auto &c : b->classes) {
         const rfim_dev::Launch ln = class_launch(b, c);
+        const bool fused = class_fused(b, c);
         const long long sites = (long long)ln.nblocks * (c.mode == 1 ? (long long)c.L * c.L * c.L / 2
                                                                       : 4ll * c.nw * c.wg);
         if (c.mode == 0 && ln.nblocks >= 16 && sites / 2 >= kSplitMinAttempts) {
@@ -1308,10 +1396,10 @@ int batch_segment(rfim_batch *b, int m, bool exch) {
             la.nblocks = (ln.nblocks / 2) & ~7;
             lb.map = ln.map + la.nblocks;
             lb.nblocks = ln.nblocks - la.nblocks;
-            lanes.push_back({la, sites / 2});
-            lanes.push_back({lb, sites / 2});
+            lanes.push_back({la, sites / 2, fused});
+            lanes.push_back({lb, sites / 2, fused});
         } else {
-            lanes.push_back({ln, sites});
+            lanes.push_back({ln, sites, fused});
         }
     }
     std::stable_sort(lanes.begin(), lanes.end(), [](const Lane &x, const Lane &y) { return x.work > y.work; });
@@ -1333,14 +1421,20 @@ int batch_segment(rfim_batch *b, int m, bool exch) {
     for (int q = 0; q < m; ++q)
         for (size_t i = 0; i < lanes.size(); ++i)
             if (lanes[i].ln.mode == 0) {
+                const int e = exch && q == m - 1 && lanes[i].fused;
                 HIPCHK(rfim_dev::launch_stream_sweep(lanes[i].ln, 0, q, 0, qs[i % nq]));
-                HIPCHK(rfim_dev::launch_stream_sweep(lanes[i].ln, 1, q, exch && q == m - 1, qs[i % nq]));
+                HIPCHK(rfim_dev::launch_stream_sweep(lanes[i].ln, 1, q, e, qs[i % nq]));
             }
     for (int j = 0; j < nside; ++j) {
         HIPCHK(hipEventRecord(b->ev_join[j], b->aux[j]));
         HIPCHK(hipStreamWaitEvent(b->stream, b->ev_join[j], 0));
     }
     if (exch) {
+        // classes whose sweeps do not write energy partials: the separate
+        // energy kernel, per item, once every lane has joined
+        for (const auto &c : b->classes)
+            if (!class_fused(b, c))
+                for (int i : c.members) HIPCHK(rfim_dev::launch_energy(b->items[i]->lattice(), b->stream));
         HIPCHK(rfim_dev::launch_exchange(b->d_lats, (int)b->items.size(), m, b->stream));
         for (rfim *h : b->items) {
             int rc;
@@ -1553,9 +1647,22 @@ int rfim_batch_synchronize(rfim_batch_t *b) {
 // between quanta, and are released when done.
 // ===================================================================
 struct rfim_pool {
-    rfim_batch core;                    // active items (compacted), classes, descriptors
+    rfim_batch core;                    // stepped items (compacted), classes, descriptors
     std::vector<rfim *> slots;          // slot id -> item (nullptr when free)
     std::vector<size_t> slot_bytes;
+    // Per slot, the schedule of a job admitted with rfim_pool_admit_job
+    // (Sec. 4: trial runs with an insertion step after each, then the
+    // production sweeps) and its progress.  Slots admitted with
+    // rfim_pool_admit have none and are driven by the caller.
+    struct Job {
+        bool scheduled = false, finished = false;
+        int trials = 0, trials_done = 0, max_insert = 0, R_cap = 0;
+        int64_t S = 0, P = 0;           // sweeps per trial, production sweeps
+        double threshold = 0.0;
+        int64_t done = 0;               // sweeps run since admission
+        uint64_t attempts = 0;          // spin-flip attempts issued
+    };
+    std::vector<Job> jobs;
     size_t budget = 0, reserved = 0;
     size_t lats_cap = 0;
     bool dirty = true;
@@ -1592,8 +1699,8 @@ int pool_apply_shape(rfim_pool *p, rfim *h) {
 int pool_build(rfim_pool *p) {
     rfim_batch &b = p->core;
     b.items.clear();
-    for (rfim *h : p->slots)
-        if (h) b.items.push_back(h);
+    for (size_t q = 0; q < p->slots.size(); ++q)
+        if (p->slots[q] && !p->jobs[q].finished) b.items.push_back(p->slots[q]);
     std::vector<rfim_batch::Class> old;
     old.swap(b.classes);
     for (int i = 0; i < (int)b.items.size(); ++i) {
@@ -1692,7 +1799,9 @@ void rfim_pool_destroy(rfim_pool_t *p) {
     delete p;
 }
 
-int rfim_pool_admit(rfim_pool_t *p, const rfim_params_t *params) {
+namespace {
+
+int pool_admit_impl(rfim_pool_t *p, const rfim_params_t *params, const rfim_pool::Job &job) {
     if (!p) return fail(RFIM_EINVAL, "pool is NULL");
     int kind = 0;
     int rc = validate(params, &kind);
@@ -1725,12 +1834,43 @@ int rfim_pool_admit(rfim_pool_t *p, const rfim_params_t *params) {
         slot = (int)p->slots.size();
         p->slots.push_back(nullptr);
         p->slot_bytes.push_back(0);
+        p->jobs.emplace_back();
     }
     p->slots[slot] = h;
     p->slot_bytes[slot] = need;
+    p->jobs[slot] = job;
     p->reserved += need;
     p->dirty = true;
     return slot;
+}
+
+}  // namespace
+
+int rfim_pool_admit(rfim_pool_t *p, const rfim_params_t *params) {
+    return pool_admit_impl(p, params, rfim_pool::Job());
+}
+
+int rfim_pool_admit_job(rfim_pool_t *p, const rfim_job_t *job) {
+    if (!p || !job) return fail(RFIM_EINVAL, "NULL argument");
+    const rfim_params_t &prm = job->params;
+    const int R_cap = prm.R_cap == 0 ? prm.R : prm.R_cap;
+    if (job->trials < 0 || job->max_insert_per_trial < 0 || std::isnan(job->rate_threshold))
+        return fail(RFIM_EINVAL, "bad job schedule: trials, max_insert_per_trial must be >= 0");
+    if (job->trials > 0 && job->sweeps_per_trial < 1)
+        return fail(RFIM_EINVAL, "bad job schedule: a trial run needs sweeps_per_trial >= 1");
+    if (job->production_sweeps < 1) return fail(RFIM_EINVAL, "bad job schedule: production_sweeps must be >= 1");
+    if ((uint64_t)job->trials * (uint64_t)std::max<int64_t>(job->sweeps_per_trial, 0) +
+            (uint64_t)job->production_sweeps > kMaxSweeps)
+        return fail(RFIM_ECAP, "job schedule passes the sweep counter limit 2^31-1");
+    rfim_pool::Job j;
+    j.scheduled = true;
+    j.trials = job->trials;
+    j.S = job->trials > 0 ? job->sweeps_per_trial : 0;
+    j.P = job->production_sweeps;
+    j.threshold = job->rate_threshold;
+    j.max_insert = job->max_insert_per_trial;
+    j.R_cap = R_cap;
+    return pool_admit_impl(p, &prm, j);
 }
 
 int rfim_pool_release(rfim_pool_t *p, int slot) {
@@ -1742,6 +1882,7 @@ int rfim_pool_release(rfim_pool_t *p, int slot) {
     free_device(h);
     delete h;
     p->slots[slot] = nullptr;
+    p->jobs[slot] = rfim_pool::Job();
     p->reserved -= p->slot_bytes[slot];
     p->slot_bytes[slot] = 0;
     p->dirty = true;
@@ -1782,11 +1923,22 @@ int rfim_pool_step(rfim_pool_t *p, int quantum, int exchange_every) {
     if (!p) return fail(RFIM_EINVAL, "pool is NULL");
     if (exchange_every < 1 || quantum < 1 || quantum % exchange_every)
         return fail(RFIM_EINVAL, "quantum must be a positive multiple of exchange_every >= 1");
-    for (rfim *h : p->slots) {
-        if (!h) continue;
+    for (size_t q = 0; q < p->slots.size(); ++q) {
+        const rfim *h = p->slots[q];
+        const rfim_pool::Job &j = p->jobs[q];
+        if (!h || j.finished) continue;
         if (h->t % (uint64_t)exchange_every)
             return fail(RFIM_ESTATE, "a pool item is not at an exchange boundary");
         if (h->t + (uint64_t)quantum > kMaxSweeps) return fail(RFIM_ECAP, "sweep counter would pass 2^31-1");
+        if (j.scheduled) {
+            // the job's next boundary (end of a trial run, or of the
+            // production sweeps) must fall on a quantum boundary
+            const int64_t next = j.trials_done < j.trials ? (int64_t)(j.trials_done + 1) * j.S
+                                                          : (int64_t)j.trials * j.S + j.P;
+            if ((next - j.done) % quantum)
+                return fail(RFIM_EINVAL, "slot %zu: its schedule boundary at sweep %lld is not a multiple of the "
+                            "quantum %d from sweep %lld", q, (long long)next, quantum, (long long)j.done);
+        }
     }
     int rc;
     if (p->dirty && (rc = pool_build(p))) return rc;
@@ -1798,12 +1950,68 @@ int rfim_pool_step(rfim_pool_t *p, int quantum, int exchange_every) {
             h->k += 1;
         }
     }
+    // progress of scheduled jobs: the insertion step at the end of each
+    // trial run (Sec. 4), completion at the end of the production sweeps
+    for (size_t q = 0; q < p->slots.size(); ++q) {
+        rfim *h = p->slots[q];
+        rfim_pool::Job &j = p->jobs[q];
+        if (!h || j.finished) continue;
+        j.attempts += (uint64_t)h->R * (uint64_t)h->N * (uint64_t)quantum;
+        if (!j.scheduled) continue;
+        j.done += quantum;
+        if (j.trials_done < j.trials && j.done == (int64_t)(j.trials_done + 1) * j.S) {
+            const int R0 = h->R;
+            if ((rc = insert_step(h, j.threshold, j.max_insert, j.R_cap)) < 0) return rc;
+            if (rc != R0) p->dirty = true;
+            ++j.trials_done;
+        }
+        if (j.trials_done == j.trials && j.done == (int64_t)j.trials * j.S + j.P) {
+            j.finished = true;
+            p->dirty = true;
+        }
+    }
+    return RFIM_OK;
+}
+
+int rfim_pool_poll(rfim_pool_t *p, int *done, int max) {
+    if (!p) return fail(RFIM_EINVAL, "pool is NULL");
+    if (max < 0 || (max > 0 && !done)) return fail(RFIM_EINVAL, "done must hold max >= 0 slot ids");
+    int n = 0;
+    for (size_t q = 0; q < p->slots.size(); ++q)
+        if (p->slots[q] && p->jobs[q].finished) {
+            if (n < max) done[n] = (int)q;
+            ++n;
+        }
+    return max == 0 ? n : std::min(n, max);
+}
+
+int rfim_pool_result(rfim_pool_t *p, int slot, rfim_result_t *res) {
+    if (!p || slot < 0 || slot >= (int)p->slots.size() || !p->slots[slot])
+        return fail(RFIM_EINVAL, "no such pool slot");
+    if (!res) return fail(RFIM_EINVAL, "result is NULL");
+    rfim *h = p->slots[slot];
+    const rfim_pool::Job &j = p->jobs[slot];
+    res->R = h->R;
+    res->finished = j.finished ? 1 : 0;
+    res->attempts = j.attempts;
+    const bool arrays = res->temps || res->energies || res->magnetizations || res->perm;
+    if (arrays && res->capacity < h->R)
+        return fail(RFIM_ECAP, "result arrays hold %d entries, the slot has %d replicas", res->capacity, h->R);
+    HIPCHK(hipStreamSynchronize(p->core.stream));
+    res->sweeps = h->t;
+    res->exchanges = h->k;
+    int rc;
+    if (res->temps) std::copy(h->T.begin(), h->T.end(), res->temps);
+    if (res->energies && (rc = rfim_energies(h, res->energies))) return rc;
+    if (res->magnetizations && (rc = rfim_magnetizations(h, res->magnetizations))) return rc;
+    if (res->perm && (rc = rfim_get_perm(h, res->perm))) return rc;
     return RFIM_OK;
 }
 
 int rfim_pool_adapt(rfim_pool_t *p, int slot, double rate_threshold, int max_insert, int R_cap) {
     rfim *h = rfim_pool_item(p, slot);
     if (!h) return RFIM_EINVAL;
+    if (p->jobs[slot].scheduled) return fail(RFIM_ESTATE, "slot %d runs its own schedule (rfim_pool_admit_job)", slot);
     if (max_insert < 0 || std::isnan(rate_threshold)) return fail(RFIM_EINVAL, "bad adapt arguments");
     if (R_cap > h->R_cap) return fail(RFIM_ECAP, "R_cap %d beyond the capacity %d given at admit", R_cap, h->R_cap);
     const int R0 = h->R;

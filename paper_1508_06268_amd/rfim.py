@@ -33,7 +33,8 @@ EXPORTS = [
     "rfim_batch_create", "rfim_batch_destroy", "rfim_batch_size", "rfim_batch_sweep",
     "rfim_batch_synchronize", "rfim_batch_item", "rfim_batch_set_shape",
     "rfim_pool_create", "rfim_pool_destroy", "rfim_pool_bytes_needed", "rfim_pool_admit",
-    "rfim_pool_step", "rfim_pool_adapt", "rfim_pool_release", "rfim_pool_item",
+    "rfim_pool_admit_job", "rfim_pool_step", "rfim_pool_poll", "rfim_pool_result",
+    "rfim_pool_adapt", "rfim_pool_release", "rfim_pool_item",
     "rfim_pool_active", "rfim_pool_reserved", "rfim_pool_set_shape", "rfim_pool_synchronize",
 ]
 
@@ -48,6 +49,18 @@ class rfim_params_t(C.Structure):
     _fields_ = [("L", C.c_int), ("R", C.c_int), ("R_cap", C.c_int), ("J", C.c_double),
                 ("h", C.c_double), ("fields", C.c_void_p), ("temps", C.c_void_p),
                 ("seed", C.c_uint64), ("realization", C.c_uint32), ("field_kind", C.c_int)]
+
+
+class rfim_job_t(C.Structure):
+    _fields_ = [("params", rfim_params_t), ("trials", C.c_int), ("sweeps_per_trial", C.c_int64),
+                ("rate_threshold", C.c_double), ("max_insert_per_trial", C.c_int),
+                ("production_sweeps", C.c_int64)]
+
+
+class rfim_result_t(C.Structure):
+    _fields_ = [("R", C.c_int), ("capacity", C.c_int), ("temps", C.c_void_p), ("energies", C.c_void_p),
+                ("magnetizations", C.c_void_p), ("perm", C.c_void_p), ("sweeps", C.c_uint64),
+                ("exchanges", C.c_uint64), ("attempts", C.c_uint64), ("finished", C.c_int)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -143,7 +156,10 @@ def load_library(path: str = LIB_PATH):
         "rfim_pool_destroy": (None, [vp]),
         "rfim_pool_bytes_needed": (sz, [C.POINTER(rfim_params_t)]),
         "rfim_pool_admit": (i32, [vp, C.POINTER(rfim_params_t)]),
+        "rfim_pool_admit_job": (i32, [vp, C.POINTER(rfim_job_t)]),
         "rfim_pool_step": (i32, [vp, i32, i32]),
+        "rfim_pool_poll": (i32, [vp, vp, i32]),
+        "rfim_pool_result": (i32, [vp, i32, C.POINTER(rfim_result_t)]),
         "rfim_pool_adapt": (i32, [vp, i32, dbl, i32, i32]),
         "rfim_pool_release": (i32, [vp, i32]),
         "rfim_pool_item": (vp, [vp, i32]),
@@ -518,8 +534,51 @@ class Pool:
         self._L[rc] = int(w.L)
         return rc
 
+    def admit_job(self, w):
+        """Admit a realization with its schedule (w.adapt: trials,
+        sweeps_per_trial, rate_threshold, max_insert_per_trial; w.sweeps:
+        production sweeps); the pool runs it to completion.  Slot id, or None
+        when the budget cannot hold it now."""
+        prm, keep = _params_of(w)
+        a = getattr(w, "adapt", None) or {}
+        job = rfim_job_t(prm, int(a.get("trials", 0)), int(a.get("sweeps_per_trial", 0)),
+                         float(a.get("rate_threshold", 0.0)), int(a.get("max_insert_per_trial", 0)),
+                         int(w.sweeps))
+        rc = load_library().rfim_pool_admit_job(self._p, C.byref(job))
+        if rc == RFIM_EBUSY:
+            return None
+        _check(rc)
+        self._L[rc] = int(w.L)
+        return rc
+
     def step(self, quantum, every):
         _check(load_library().rfim_pool_step(self._p, int(quantum), int(every)))
+
+    def poll(self):
+        """Slot ids of finished jobs not yet released (ascending)."""
+        n = _check(load_library().rfim_pool_poll(self._p, None, 0))
+        if n == 0:
+            return []
+        buf = (C.c_int * n)()
+        m = _check(load_library().rfim_pool_poll(self._p, buf, n))
+        return list(buf[:m])
+
+    def result(self, slot) -> dict:
+        """State of a slot through rfim_pool_result: R, temperatures,
+        energies, magnetisations and permutation by slot, counters, the
+        attempts issued and whether its schedule is complete."""
+        res = rfim_result_t()
+        res.capacity = 0
+        _check(load_library().rfim_pool_result(self._p, int(slot), C.byref(res)))
+        R = res.R
+        T = np.zeros(R, dtype=np.float64)
+        E = np.zeros(R, dtype=np.float64)
+        M = np.zeros(R, dtype=np.int64)
+        P = np.zeros(R, dtype=np.int32)
+        res = rfim_result_t(0, R, T.ctypes.data, E.ctypes.data, M.ctypes.data, P.ctypes.data, 0, 0, 0, 0)
+        _check(load_library().rfim_pool_result(self._p, int(slot), C.byref(res)))
+        return dict(R=res.R, temps=T, energies=E, magnetizations=M, perm=P, sweeps=res.sweeps,
+                    exchanges=res.exchanges, attempts=res.attempts, finished=bool(res.finished))
 
     def adapt(self, slot, rate_threshold, max_insert, R_cap) -> int:
         return _check(load_library().rfim_pool_adapt(self._p, int(slot), float(rate_threshold),

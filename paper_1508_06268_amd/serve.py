@@ -10,9 +10,12 @@ requests as they finish; requests that arrive while others run join the
 running set at the next quantum boundary.  It reports per-request latency
 (completion - arrival) with p50/p99, throughput and utilization.
 
-The loop talks to an engine (admit / step / adapt / collect / release);
-`PoolEngine` drives the GPU pool of librfim.  Any object with the same
-methods works (the tests use a CPU engine and a virtual clock).
+The loop talks to an engine (admit / step / poll / result / release):
+admit hands over a request with its whole schedule, the engine runs the
+insertion steps and reports finished requests through poll.  `PoolEngine`
+drives the GPU pool of librfim through rfim_pool_admit_job,
+rfim_pool_step, rfim_pool_poll and rfim_pool_result.  Any object with the
+same methods works (the tests use a CPU engine and a virtual clock).
 """
 from __future__ import annotations
 
@@ -64,7 +67,8 @@ class PoolEngine:
         return self.pool.bytes_needed(spec)
 
     def admit(self, spec):
-        return self.pool.admit(spec)
+        """Slot id with the request's schedule, or None if the budget is full."""
+        return self.pool.admit_job(spec)
 
     def step(self, quantum: int, every: int) -> None:
         self.pool.step(quantum, every)
@@ -72,28 +76,17 @@ class PoolEngine:
     def sync(self) -> None:
         self.pool.synchronize()
 
-    def adapt(self, slot, rate_threshold, max_insert, R_cap) -> int:
-        return self.pool.adapt(slot, rate_threshold, max_insert, R_cap)
+    def poll(self):
+        return self.pool.poll()
 
-    def collect(self, slot) -> dict:
-        it = self.pool.item(slot)
-        return dict(R=it.R, temps=it.temps(), energies=it.energies(), perm=it.perm(),
-                    magnetizations=it.magnetizations())
+    def result(self, slot) -> dict:
+        return self.pool.result(slot)
 
     def release(self, slot) -> None:
         self.pool.release(slot)
 
     def close(self):
         self.pool.close()
-
-
-@dataclasses.dataclass
-class _Active:
-    req: Request
-    out: Outcome
-    done: int = 0           # sweeps run so far
-    trials_done: int = 0
-    R: int = 0              # current replica count
 
 
 def schedule(spec):
@@ -120,6 +113,8 @@ class Server:
         trials, S, P, every = schedule(spec)
         if every != self.every:
             raise ValueError("request exchange interval %d differs from the server's %d" % (every, self.every))
+        if trials < 0 or (trials > 0 and S < 1) or P < 1:
+            raise ValueError("a request needs production sweeps >= 1 and, with trial runs, trial sweeps >= 1")
         if S % self.quantum or P % self.quantum:
             raise ValueError("trial and production sweeps must be multiples of the quantum %d" % self.quantum)
 
@@ -127,7 +122,7 @@ class Server:
         eng = self.engine
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         waiting: collections.deque = collections.deque()
-        active: Dict[int, _Active] = {}
+        active: Dict[int, Outcome] = {}
         outcomes: Dict[int, Outcome] = {}
         t0 = self.clock()
         busy_steps = 0
@@ -157,7 +152,7 @@ class Server:
                     break
                 waiting.popleft()
                 out.admitted = now
-                active[slot] = _Active(req, out, R=int(req.spec.R))
+                active[slot] = out
             if not active:
                 if pending:
                     self.sleep(max(0.0, pending[0].arrival - (self.clock() - t0)))
@@ -166,25 +161,17 @@ class Server:
             eng.step(self.quantum, self.every)
             eng.sync()
             busy_steps += 1
-            now = self.clock() - t0
-            for slot in list(active):
-                st = active[slot]
-                spec = st.req.spec
-                trials, S, P, _ = schedule(spec)
-                st.out.attempts += st.R * int(spec.L) ** 3 * self.quantum
-                st.done += self.quantum
-                if st.trials_done < trials and st.done == (st.trials_done + 1) * S:
-                    a = spec.adapt
-                    st.R = eng.adapt(slot, a["rate_threshold"], a["max_insert_per_trial"], a["R_cap"])
-                    st.trials_done += 1
-                if st.trials_done == trials and st.done == trials * S + P:
-                    res = eng.collect(slot)
-                    eng.release(slot)
-                    st.out.finished = self.clock() - t0
-                    for k, v in res.items():
-                        setattr(st.out, k, v)
-                    outcomes[st.req.rid] = st.out
-                    del active[slot]
+            # the engine runs each request's schedule (insertion steps after
+            # its trial runs) and reports the finished ones
+            for slot in eng.poll():
+                out = active.pop(slot)
+                res = eng.result(slot)
+                eng.release(slot)
+                out.finished = self.clock() - t0
+                for k in ("R", "temps", "energies", "perm", "magnetizations", "attempts"):
+                    setattr(out, k, res[k])
+                out.attempts = int(out.attempts)
+                outcomes[out.rid] = out
         wall = self.clock() - t0
         done = [o for o in outcomes.values() if o.finished is not None]
         lat = np.array([o.latency for o in done]) if done else np.zeros(0)

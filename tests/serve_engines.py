@@ -1,10 +1,27 @@
 """A CPU engine for the serving loop, built on the oracle (test
-infrastructure): same admit / step / adapt / collect / release protocol as
-the GPU pool, with a byte budget and a virtual clock that advances with the
-work done."""
+infrastructure): the same admit / step / poll / result / release protocol as
+the GPU pool (which runs each request's schedule itself: the insertion step
+after every trial run, completion after the production sweeps), with a byte
+budget and a virtual clock that advances with the work done."""
 import numpy as np
 
 from oracle.oracle import Oracle
+
+
+class _Job:
+    def __init__(self, o, need, spec):
+        a = getattr(spec, "adapt", None) or {}
+        self.o, self.need, self.spec = o, need, spec
+        self.trials = int(a.get("trials", 0))
+        self.S = int(a.get("sweeps_per_trial", 0)) if self.trials else 0
+        self.P = int(spec.sweeps)
+        self.threshold = float(a.get("rate_threshold", 0.0))
+        self.max_insert = int(a.get("max_insert_per_trial", 0))
+        self.R_cap = int(getattr(spec, "R_cap", 0) or spec.R)
+        self.done = 0
+        self.trials_done = 0
+        self.finished = False
+        self.attempts = 0
 
 
 class OracleEngine:
@@ -32,35 +49,48 @@ class OracleEngine:
         slot = 0
         while slot in self.slots:
             slot += 1
-        self.slots[slot] = (o, need, spec)
+        self.slots[slot] = _Job(o, need, spec)
         self.reserved += need
         self.log.append(("admit", slot))
         return slot
 
     def step(self, quantum, every):
         work = 0
-        for slot, (o, _, spec) in sorted(self.slots.items()):
-            o.sweep(quantum, every)
-            work += o.R * spec.L ** 3 * quantum
+        running = 0
+        for slot, j in sorted(self.slots.items()):
+            if j.finished:
+                continue
+            running += 1
+            j.o.sweep(quantum, every)
+            n = j.o.R * j.spec.L ** 3 * quantum
+            j.attempts += n
+            work += n
+            j.done += quantum
+            if j.trials_done < j.trials and j.done == (j.trials_done + 1) * j.S:
+                j.o.insert_step(j.threshold, j.max_insert, j.R_cap)
+                j.trials_done += 1
+            if j.trials_done == j.trials and j.done == j.trials * j.S + j.P:
+                j.finished = True
         if self.clock is not None:
             self.clock.advance(work * self.ns_per_attempt * 1e-9)
-        self.log.append(("step", len(self.slots)))
+        self.log.append(("step", running))
 
     def sync(self):
         pass
 
-    def adapt(self, slot, rate_threshold, max_insert, R_cap):
-        return self.slots[slot][0].insert_step(rate_threshold, max_insert, R_cap)
+    def poll(self):
+        return [s for s, j in sorted(self.slots.items()) if j.finished]
 
-    def collect(self, slot):
-        o = self.slots[slot][0]
+    def result(self, slot):
+        j = self.slots[slot]
+        o = j.o
         return dict(R=o.R, temps=o.temps(), energies=o.energies(), perm=o.perm(),
-                    magnetizations=o.magnetizations())
+                    magnetizations=o.magnetizations(), attempts=j.attempts, finished=j.finished)
 
     def release(self, slot):
-        o, need, _ = self.slots.pop(slot)
-        self.reserved -= need
-        o.close()
+        j = self.slots.pop(slot)
+        self.reserved -= j.need
+        j.o.close()
         self.log.append(("release", slot))
 
 

@@ -59,6 +59,22 @@ def test_null_handle_calls_fail_cleanly(rfim_mod):
     lib.rfim_destroy(None)
 
 
+def test_pool_job_calls_reject_bad_arguments(rfim_mod):
+    """rfim_pool_admit_job, rfim_pool_poll and rfim_pool_result validate
+    their arguments before any device work."""
+    import ctypes as C
+
+    from paper_1508_06268_amd import rfim as B
+
+    lib = rfim_mod.load_library()
+    job = B.rfim_job_t()
+    assert lib.rfim_pool_admit_job(None, C.byref(job)) == -1
+    assert lib.rfim_pool_poll(None, None, 0) == -1
+    res = B.rfim_result_t()
+    assert lib.rfim_pool_result(None, 0, C.byref(res)) == -1
+    assert b"no such pool slot" in lib.rfim_last_error()
+
+
 def test_null_handle_getters_and_setters_fail_cleanly(rfim_mod):
     lib = rfim_mod.load_library()
     assert lib.rfim_set_concurrency(None, 0) == -1

@@ -149,3 +149,41 @@ def test_batch_items_measure_fourier_like_single_runs(rfim_mod):
     assert np.array_equal(got, g.fourier())
     g.close()
     b.close()
+
+
+@pytest.mark.parametrize("shape", [(0, 1, 64), (0, 2, 64)])
+def test_batch_class_without_fused_energy_matches_single_runs(rfim_mod, oracle_mod, shape):
+    """An L=128 class whose streaming shape has more than 1024 workgroups per
+    replica: its sweep kernels do not write energy partials, and the batch
+    runs the separate energy kernel for its items before the exchange step.
+    Items must equal the same realizations run alone (and the oracle for
+    +-1 fields), with accepted exchanges in the run."""
+    specs = []
+    for rho, kind in enumerate(("b", "g", "b")):
+        L, R = 128, 3
+        f = W.bimodal_fields(L, [31, rho]) if kind == "b" else W.gaussian_fields(L, [31, rho])
+        specs.append(W.Realization(L=L, R=R, J=1.0, h=1.0, fields=f, temps=np.array([2.0, 2.2, 2.4]),
+                                   seed=12, realization=rho, sweeps=0, every=2))
+    b = rfim_mod.Batch(specs)
+    b.set_shape(128, 0, *shape)
+    b.set_shape(128, 1, *shape)
+    b.sweep(6, 2)
+    b.synchronize()
+    accepted = 0
+    for q, w in enumerate(specs):
+        g = rfim_mod.Rfim(w.L, w.R, w.J, w.h, w.fields, w.temps, seed=w.seed, realization=w.realization)
+        g.set_launch_shape(*shape)
+        g.sweep(6, 2)
+        it = b.item(q)
+        assert np.array_equal(it.spins(), g.spins()), q
+        assert np.array_equal(it.perm(), g.perm()), q
+        assert np.array_equal(it.energies(), g.energies()), q
+        accepted += int(it.exchange_stats()[1].sum())
+        if q % 2 == 0:
+            o = oracle_mod.Oracle(w.L, w.R, w.J, w.h, w.fields, w.temps, seed=w.seed, realization=w.realization)
+            o.sweep(6, 2)
+            assert_same_state(it, o, "non-fused batch item %d" % q)
+            o.close()
+        g.close()
+    assert accepted > 0
+    b.close()

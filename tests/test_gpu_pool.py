@@ -99,3 +99,82 @@ def test_pool_budget_admission(rfim_mod):
     pool.step(20, 10)
     pool.synchronize()
     pool.close()
+
+
+def test_pool_jobs_complete_through_the_c_abi(rfim_mod, oracle_mod):
+    """Jobs admitted with their schedule (rfim_pool_admit_job) run to the end
+    inside the library: rfim_pool_step runs each insertion step when a trial
+    run ends, rfim_pool_poll reports exactly the finished slots after each
+    step (finished slots are stepped no further), and rfim_pool_result
+    returns their state.  +-1 jobs equal the oracle's adapt_temps + sweep;
+    Gaussian jobs equal the same realization run alone."""
+    import ctypes as C
+
+    from paper_1508_06268_amd import rfim as B
+
+    lib = rfim_mod.load_library()
+    plan = [(8, 8, "b", 1, 40, 40), (16, 6, "g", 1, 20, 60), (32, 4, "b", 2, 20, 20), (8, 5, "b", 0, 0, 20)]
+    reqs, keep = [], []
+    for q, (L, R, kind, trials, S, P) in enumerate(plan):
+        rq = _req(q, 0.0, L, R, kind, trial=S, prod=P)
+        rq.spec.adapt["trials"] = trials
+        reqs.append(rq)
+    pool = lib.rfim_pool_create(1 << 30, None)
+    assert pool
+    slots = []
+    for rq in reqs:
+        w = rq.spec
+        prm, arrays = B._params_of(w)
+        keep.append(arrays)
+        a = w.adapt
+        job = B.rfim_job_t(prm, a["trials"], a["sweeps_per_trial"], a["rate_threshold"],
+                           a["max_insert_per_trial"], w.sweeps)
+        slot = lib.rfim_pool_admit_job(pool, C.byref(job))
+        assert slot >= 0, B.last_error()
+        slots.append(slot)
+    ends = {s: rq.spec.adapt["trials"] * rq.spec.adapt["sweeps_per_trial"] + rq.spec.sweeps
+            for s, rq in zip(slots, reqs)}
+    done_at = {}
+    buf = (C.c_int * 16)()
+    t = 0
+    while len(done_at) < len(slots):
+        assert lib.rfim_pool_step(pool, 20, 10) == 0, B.last_error()
+        t += 20
+        n = lib.rfim_pool_poll(pool, buf, 16)
+        assert lib.rfim_pool_poll(pool, None, 0) == n
+        finished = set(buf[:n])
+        assert finished == {s for s, e in ends.items() if e <= t}, (t, finished)
+        for s in finished:
+            done_at.setdefault(s, t)
+        assert t <= 200
+    for s, rq in zip(slots, reqs):
+        w = rq.spec
+        a = w.adapt
+        res = B.rfim_result_t()
+        assert lib.rfim_pool_result(pool, s, C.byref(res)) == 0
+        R = res.R
+        T, E = np.zeros(R), np.zeros(R)
+        M, P = np.zeros(R, dtype=np.int64), np.zeros(R, dtype=np.int32)
+        res = B.rfim_result_t(0, R, T.ctypes.data, E.ctypes.data, M.ctypes.data, P.ctypes.data, 0, 0, 0, 0)
+        assert lib.rfim_pool_result(pool, s, C.byref(res)) == 0
+        assert res.finished == 1
+        assert res.sweeps == ends[s] and res.exchanges == ends[s] // 10
+        if w.fields.min() == -1.0 and np.all(np.abs(w.fields) == 1.0):
+            o = oracle_mod.Oracle(w.L, w.R, w.J, w.h, w.fields, w.temps, seed=w.seed, realization=w.realization,
+                                  R_cap=w.R_cap)
+            if a["trials"]:
+                o.adapt_temps(a["trials"], a["sweeps_per_trial"], a["every"], a["rate_threshold"],
+                              a["max_insert_per_trial"], a["R_cap"])
+            o.sweep(w.sweeps, w.every)
+            assert R == o.R
+            assert np.array_equal(T, o.temps()) and np.array_equal(P, o.perm())
+            assert np.array_equal(E, o.energies()) and np.array_equal(M, o.magnetizations())
+            o.close()
+        else:
+            g = _alone(rfim_mod, w)
+            assert R == g.R and np.array_equal(P, g.perm()) and np.array_equal(M, g.magnetizations())
+            assert np.allclose(E, g.energies(), rtol=1e-12, atol=1e-9)
+            g.close()
+        assert lib.rfim_pool_release(pool, s) == 0
+    assert lib.rfim_pool_poll(pool, None, 0) == 0
+    lib.rfim_pool_destroy(pool)

@@ -119,6 +119,19 @@ def test_request_larger_than_budget_fails_and_alloc_failure_is_isolated():
     assert res["stats"]["failed"] == 5 and res["stats"]["completed"] == 0
 
 
+def test_empty_schedules_are_rejected():
+    """A request whose schedule can never finish (an empty trial run, no
+    production sweeps) fails at admission instead of running forever."""
+    no_trial = _req(20, 0.0, L=4, R=4, trial=0)
+    no_trial.spec.adapt["trials"] = 1            # one trial run of 0 sweeps
+    no_prod = _req(21, 0.0, L=4, R=4, prod=0)
+    srv, eng, _ = _server(10 ** 9)
+    res = srv.run([no_trial, no_prod] + _mix())
+    out = res["outcomes"]
+    assert out[20].error and out[21].error
+    assert res["stats"]["completed"] == len(_mix())
+
+
 def test_latency_statistics():
     srv, _, _ = _server(10 ** 9)
     st = srv.run(_mix())["stats"]
