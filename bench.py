@@ -34,21 +34,21 @@ METRIC = "spin-flip attempts/ns & % HBM roofline at L=64; realizations/s + p99 l
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_1508_06268_amd", "csrc", "rfim_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_pow2_l64_r192_traffic.txt")
+VALU_FILE = os.path.join(ROOT, "profiles", "sweep_pow2_l64_r192_valu.txt")
 # Algorithmic HBM bytes per spin-flip attempt of one half-sweep with one-byte
 # spins: read the site (1), read the other colour once (1), read the field
-# (1 for +-1 fields, 4 for FP32 fields), write the site (1).
+# (1 for +-1 fields, 4 for FP32 fields), write the site (1).  The field is
+# shared by every replica of a realization, so a launch over R replicas
+# needs it once: 3 + f/R bytes per attempt is the floor with perfect reuse.
 BYTES_PER_ATTEMPT = {0: 4.0, 1: 7.0}
-# The half-sweep is bound by the vector ALU (Philox4x32-10), so its roofline
-# is the VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12
-# full-rate 32-bit lane-op slots per second.  Algorithmic slots per attempt
-# (+-1 fields), with the cheapest gfx950 instruction for each required step:
-#   Philox block (4 attempts): 20 products 32x32->64 at 2 slots + 20 XOR3
-#     at 1 slot = 60 slots;
-#   Metropolis on four packed sites: neighbour counts 3, threshold index 2,
-#     per-site byte extract 4, compare 4, flip assembly 4, new word 1 = 18.
-#   (60 + 18) / 4 = 19.5 slots per attempt.
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-VALU_SLOTS_PER_ATTEMPT = 19.5
+FIELD_BYTES = {0: 1.0, 1: 4.0}
+# Vector ALU issue: 256 CUs x 4 SIMDs, a wave64 instruction occupies its SIMD
+# for 4 cycles at full rate, so 256 x 4 x 2.4e9 / 4 = 0.614e12 wave-instruction
+# slots per second.  The VALU figure below counts the kernel's measured
+# VALU instructions per wave (profiles/sweep_pow2_l64_r192_valu.txt) at one
+# slot each.
+CUS, SIMDS, CLOCK_HZ = 256, 4, 2.4e9
+WAVE_SLOTS_PER_S = CUS * SIMDS * CLOCK_HZ / 4.0
 
 
 def log(msg):
@@ -59,17 +59,27 @@ def kernel_hash() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(bytes_algo_per_launch):
-    """HBM bytes per launch of the sweep kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def _profile_value(path, pattern):
+    """A figure from a committed rocprofv3 summary, if it was taken on the
+    current kernel source (same hash), else None."""
+    if not os.path.exists(path):
         return None
-    text = open(TRAFFIC_FILE).read()
+    text = open(path).read()
     m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
-    m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m_hash or not m_bytes or m_hash.group(1) != kernel_hash():
+    m_val = re.search(pattern, text)
+    if not m_hash or not m_val or m_hash.group(1) != kernel_hash():
         return None
-    return float(m_bytes.group(1))
+    return float(m_val.group(1))
+
+
+def measured_traffic():
+    """HBM bytes per launch of the sweep kernel (FETCH_SIZE + WRITE_SIZE)."""
+    return _profile_value(TRAFFIC_FILE, r"hbm_bytes_per_launch:\s*([0-9.eE+]+)")
+
+
+def measured_valu_per_wave():
+    """VALU instructions per wave of the sweep kernel (SQ_INSTS_VALU / SQ_WAVES)."""
+    return _profile_value(VALU_FILE, r"VALU instructions per wave:\s*([0-9.]+)")
 
 
 def run_realization(h, w, stream, torch):
@@ -87,20 +97,48 @@ def run_realization(h, w, stream, torch):
     return attempts
 
 
-def cpu_baseline(w, sweeps=20):
-    """The CPU oracle on a bounded sample of the same workload: the initial
-    replica set for `sweeps` sweeps with exchange every 10."""
+def host_info():
+    """What the CPU baseline ran on: model name, nproc and the CPUs this
+    process may use."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": os.cpu_count(), "cpus_allowed": allowed}
+
+
+def oracle_timed_build():
+    """The oracle built for timing on this host (-O3 -march=native
+    -ffp-contract=off) in a private directory."""
+    import tempfile
+
     from oracle import oracle as O
 
-    O.build()
+    return O.timed_build(tempfile.mkdtemp(prefix="rfim_oracle_"))
+
+
+def cpu_baseline(w, lib_path, sweeps=20):
+    """The CPU oracle on a bounded sample of the same workload: the initial
+    replica set for `sweeps` sweeps with exchange every 10, one thread."""
+    from oracle import oracle as O
+
+    O.use_library(lib_path)
     o = O.Oracle(w.L, w.R, w.J, w.h, w.fields, w.temps, seed=w.seed)
     t0 = time.perf_counter()
     o.sweep(sweeps, w.every)
     dt = time.perf_counter() - t0
     att = w.R * w.L ** 3 * sweeps
     return {"value": att / (dt * 1e9), "unit": "spin-flip attempts/ns", "cores": 1, "kind": "oracle",
-            "sample": "L=%d, R=%d, %d sweeps with exchange every %d (%.2e attempts, %.1f s, 1 thread)"
-                      % (w.L, w.R, sweeps, w.every, att, dt)}
+            "sample": "L=%d, R=%d, %d sweeps with exchange every %d (%.2e attempts, %.1f s, 1 thread; "
+                      "gcc -O3 -march=native -ffp-contract=off)" % (w.L, w.R, sweeps, w.every, att, dt)}
 
 
 def kernel_only(torch, P, W, sweeps):
@@ -126,12 +164,13 @@ def copy_only(torch, nbytes, reps=5):
     log("copy mode: %d copies of %d bytes (read %d, write %d per copy)" % (reps, nbytes, nbytes, nbytes))
 
 
-def cpu_worker(q, sweeps=20):
+def cpu_worker(q, lib_path, sweeps=20):
     """Child process of the all-cores figure: the oracle on realization q of
     the L=64 workload (no GPU, no torch), one JSON line on stdout."""
     from paper_1508_06268_amd import workloads as W
     from oracle import oracle as O
 
+    O.use_library(lib_path)
     w = W.adaptive_l64()
     o = O.Oracle(w.L, w.R, w.J, w.h, W.bimodal_fields(w.L, [9, q]), w.temps, seed=w.seed, realization=q)
     t0 = time.perf_counter()
@@ -140,18 +179,16 @@ def cpu_worker(q, sweeps=20):
     print(json.dumps({"attempts": w.R * w.L ** 3 * sweeps, "seconds": dt}), flush=True)
 
 
-def cpu_all_cores(procs):
+def cpu_all_cores(procs, lib_path):
     """`procs` independent oracle processes on different realizations at
-    once (started as child processes of a fresh interpreter); aggregate
-    attempts over the wall time of the slowest."""
+    once (child processes of a fresh interpreter that never touch the GPU);
+    aggregate attempts over the wall time of the slowest."""
     import subprocess
 
-    from oracle import oracle as O
-
-    O.build()
     t0 = time.perf_counter()
-    ps = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", str(q)],
-                           stdout=subprocess.PIPE, cwd=ROOT) for q in range(procs)]
+    ps = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", str(q),
+                            "--cpu-worker-lib", lib_path], stdout=subprocess.PIPE, cwd=ROOT)
+          for q in range(procs)]
     outs = [json.loads(p.communicate()[0].decode().strip().splitlines()[-1]) for p in ps]
     wall = time.perf_counter() - t0
     if any(p.returncode != 0 for p in ps):
@@ -309,13 +346,47 @@ def served_leg(torch, P, W, n=2000, rate=50.0, budget=200 << 30, quantum=50, sin
             "shapes": {"L%d_%s" % (L, "pm1" if k == 0 else "gauss"): list(v) for (L, k), v in sorted(shapes.items())}}
 
 
+def paper_scale_leg(torch, P, W, reps=3):
+    """Plain method at paper scale: L=32, Gaussian FP32 fields h=2, R=64
+    geometric in [1, 6], 10^4 sweeps with an exchange every 10, on the
+    handle's default shape; median of `reps` whole runs, each timed with
+    events on the handle's stream."""
+    w = W.paper_scale_l32()
+    stream = torch.cuda.Stream()
+    times = []
+    shape = None
+    for _ in range(reps):
+        h = P.Rfim(w.L, w.R, w.J, w.h, w.fields, w.temps, seed=w.seed, stream=stream)
+        shape = h.launch_shape()
+        h.sweep(10, 10)
+        stream.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        h.sweep(w.sweeps, w.every)
+        e1.record(stream)
+        stream.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+        h.close()
+    dt = float(np.median(times))
+    attempts = w.R * w.L ** 3 * w.sweeps
+    rate = attempts / dt / 1e9
+    bpa = 3.0 + FIELD_BYTES[1] / w.R
+    log("paper scale (L=32, R=64, Gaussian, 10^4 sweeps): %.1f ms -> %.1f attempts/ns" % (dt * 1e3, rate))
+    return {"workload": "paper_scale_l32", "L": w.L, "R": w.R, "fields": "gaussian fp32", "h": w.h,
+            "sweeps": w.sweeps, "exchange_every": w.every, "launch_shape": list(shape),
+            "seconds": round(dt, 5), "attempts_per_ns": round(rate, 1),
+            "hbm_gbs_at_7B": round(rate * 7.0, 1), "hbm_gbs_at_shared_field_bytes": round(rate * bpa, 1),
+            "bytes_per_attempt_shared_field": round(bpa, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="adaptive_l64", choices=["adaptive_l64", "served_stream"],
-                    help="served_stream: the continuous-batching serving run (its own JSON line)")
+                    help="served_stream: only the continuous-batching serving run (its own JSON line)")
     ap.add_argument("--production-sweeps", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="bench", choices=["bench", "kernel", "streaming", "copy"],
@@ -323,10 +394,12 @@ def main():
                          "HBM-streaming leg; copy: a plain copy of --copy-bytes (counter calibration)")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-realizations leg")
+    ap.add_argument("--no-served", action="store_true", help="skip the served-stream leg")
     ap.add_argument("--cpu-worker", type=int, default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-worker-lib", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_worker is not None:
-        cpu_worker(args.cpu_worker)
+        cpu_worker(args.cpu_worker, args.cpu_worker_lib)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: a realization runs on a single MI355X and sharding "
@@ -361,32 +434,38 @@ def main():
                for _ in range(args.warmup + args.steps)]
     torch.cuda.synchronize()
 
+    warm_ms = []
     for q in range(args.warmup):
         t0 = time.perf_counter()
         run_realization(handles[q], w, stream, torch)
         handles[q].synchronize()
-        log("warmup %d: %.3f s, R=%d" % (q, time.perf_counter() - t0, handles[q].R))
+        warm_ms.append((time.perf_counter() - t0) * 1e3)
+        log("warmup %d: %.1f ms, R=%d" % (q, warm_ms[-1], handles[q].R))
 
+    # Timed region: K whole realizations back to back on one stream; an
+    # event after each one gives the per-step times without synchronizing.
     torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     attempts = 0
-    ev0.record(stream)
+    step_R = []
+    evs[0].record(stream)
     t0 = time.perf_counter()
     for q in range(args.steps):
         h = handles[args.warmup + q]
         attempts += run_realization(h, w, stream, torch)
-        log("step %d issued, R=%d" % (q, h.R))
-    ev1.record(stream)
+        evs[q + 1].record(stream)
+        step_R.append(h.R)
     stream.synchronize()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
+    gpu_ms = evs[0].elapsed_time(evs[-1])
+    step_ms = [evs[q].elapsed_time(evs[q + 1]) for q in range(args.steps)]
     elapsed_s = max(wall, gpu_ms / 1e3)
     value = attempts / (elapsed_s * 1e9)
     R_final = handles[-1].R
     log("timed: %d steps, %.2e attempts, %.3f s wall, %.3f s events -> %.1f attempts/ns"
         % (args.steps, attempts, wall, gpu_ms / 1e3, value))
+    log("step ms: %s" % " ".join("%.1f" % t for t in step_ms))
 
     # Roofline leg: the dominant kernel (one half-sweep of every replica) at
     # the production shape, timed with events on the handle's stream.
@@ -421,44 +500,62 @@ def main():
     attempts_per_launch = R_final * w.L ** 3 // 2
     bytes_per_launch = BYTES_PER_ATTEMPT[kind] * attempts_per_launch
     hbm_gbs = bytes_per_launch / (launch_us * 1e-6) / 1e9
-    alu_tops = VALU_SLOTS_PER_ATTEMPT * attempts_per_launch / (launch_us * 1e-6) / 1e12
-    traffic = measured_traffic(bytes_per_launch)
-    roofline = {"bound": "alu", "achieved": round(alu_tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
-                "unit": "TOP/s", "frac": round(alu_tops / VALU_PEAK_TOPS, 4), "traffic": traffic,
-                "kernel": "sweep_pow2<bimodal, %d dwords x %d threads>" % (nw, wg),
-                "launch_us": round(launch_us, 3),
-                "attempts_per_launch": attempts_per_launch,
-                "ops_per_attempt": VALU_SLOTS_PER_ATTEMPT,
+    traffic = measured_traffic()
+    # VALU: the kernel's measured instructions per wave (1024 attempts per
+    # wave) against the issue rate of the chip, when the counter summary
+    # matches the current kernel source
+    valu_per_wave = measured_valu_per_wave()
+    waves_per_launch = attempts_per_launch / 1024.0
+    alu = None
+    if valu_per_wave:
+        inst_rate = valu_per_wave * waves_per_launch / (launch_us * 1e-6)
+        alu = {"achieved": round(inst_rate / 1e12, 4), "peak": round(WAVE_SLOTS_PER_S / 1e12, 4),
+               "unit": "T wave-instructions/s", "frac": round(inst_rate / WAVE_SLOTS_PER_S, 4),
+               "valu_per_wave": valu_per_wave,
+               "two_streams_frac": round(valu_per_wave * waves_per_launch / (split_us * 1e-6)
+                                         / WAVE_SLOTS_PER_S, 4)}
+    roofline = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(hbm_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "sweep_pow2<bimodal, %d dwords x %d threads>, one launch over R=%d" % (nw, wg, R_final),
+                "launch_us": round(launch_us, 3), "attempts_per_launch": attempts_per_launch,
+                "bytes_per_attempt": BYTES_PER_ATTEMPT[kind], "bytes_per_launch": bytes_per_launch,
                 "attempts_per_ns_kernel": round(attempts_per_launch / (launch_us * 1e3), 1),
-                "hbm": {"achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
-                        "bytes_per_launch": bytes_per_launch, "bytes_per_attempt": BYTES_PER_ATTEMPT[kind]},
+                "alu": alu,
                 "two_streams": {"half_sweep_us": round(split_us, 3),
                                 "attempts_per_ns": round(attempts_per_launch / (split_us * 1e3), 1),
-                                "alu_frac": round(VALU_SLOTS_PER_ATTEMPT * attempts_per_launch
-                                                  / (split_us * 1e-6) / 1e12 / VALU_PEAK_TOPS, 4),
                                 "hbm_frac": round(bytes_per_launch / (split_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}}
-    log("roofline: %.2f us per half-sweep launch, %.0f GB/s algorithmic (%.1f%% of HBM), "
-        "%.1f TOP/s VALU (%.1f%%); two streams: %.2f us per half-sweep"
-        % (launch_us, hbm_gbs, 100 * hbm_gbs / HBM_PEAK_GBS, alu_tops, 100 * alu_tops / VALU_PEAK_TOPS, split_us))
+    log("roofline: %.2f us per half-sweep launch, %.0f GB/s algorithmic (%.1f%% of HBM); "
+        "two streams: %.2f us per half-sweep" % (launch_us, hbm_gbs, 100 * hbm_gbs / HBM_PEAK_GBS, split_us))
+    if alu:
+        log("VALU: %.1f%% of issue slots (one launch), %.1f%% (two streams)"
+            % (100 * alu["frac"], 100 * alu["two_streams_frac"]))
 
     for hh in handles:
         hh.close()
     streaming = hbm_streaming_leg(torch, P, W)
     roofline["hbm_streaming"] = streaming
+    paper_scale = paper_scale_leg(torch, P, W)
     batched = None if args.no_batched else batched_leg(torch, P, W)
+    served = None if args.no_served else served_leg(torch, P, W)
 
     cpu = None
     if not args.no_cpu_baseline:
+        log("cpu baseline: building the oracle for this host")
+        lib_path = oracle_timed_build()
         log("cpu baseline: oracle on a bounded sample")
-        cpu = cpu_baseline(w)
-        procs = max(1, min(16, os.cpu_count() or 1))
+        cpu = cpu_baseline(w, lib_path)
+        info = host_info()
+        # the GPU's host share is 16 cores: one process per core of it
+        procs = max(1, min(16, info["cpus_allowed"]))
         log("cpu baseline: %d oracle processes at once" % procs)
-        cpu["all_cores"] = cpu_all_cores(procs)
+        cpu["all_cores"] = cpu_all_cores(procs, lib_path)
+        cpu["host"] = info
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "spin-flip attempts/ns", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(elapsed_s * 1e3 / args.steps, 3),
+        "step_ms": [round(t, 2) for t in step_ms], "step_R": step_R,
+        "warmup_ms": [round(t, 2) for t in warm_ms],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
         "data": "synthetic",
         "config": {"workload": "adaptive_l64", "L": w.L, "R0": w.R, "R_final": R_final,
@@ -469,7 +566,9 @@ def main():
                    "attempts_per_step": attempts // args.steps},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "paper_scale_l32": paper_scale,
         "batched": batched,
+        "served": served,
     }
     print(json.dumps(out), flush=True)
 

@@ -33,14 +33,40 @@ def build(force: bool = False) -> str:
     return LIB_PATH
 
 
+def timed_build(out_dir: str) -> str:
+    """The same source built for timing on this host (-O3 -march=native,
+    still -ffp-contract=off) into out_dir; the tested library is left as it
+    is.  Returns the path of the build."""
+    import subprocess
+
+    os.makedirs(out_dir, exist_ok=True)
+    path = os.path.join(out_dir, "liboracle_native.so")
+    tmp = path + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-std=c99", "-O3", "-march=native", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+           "-shared", "-o", tmp] + SOURCES + ["-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, path)
+    return path
+
+
 _lib = None
+_lib_path = None
+
+
+def use_library(path: str) -> None:
+    """Load the oracle from `path` (a timed_build) instead of the tested
+    build; call before the first Oracle is made."""
+    global _lib, _lib_path
+    _lib = None
+    _lib_path = path
 
 
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = C.CDLL(LIB_PATH)
+        if _lib_path is None:
+            build()
+        L = C.CDLL(_lib_path or LIB_PATH)
         vp, i32, i64, u32, u64, dbl = C.c_void_p, C.c_int, C.c_int64, C.c_uint32, C.c_uint64, C.c_double
         L.orc_create.restype = vp
         L.orc_create.argtypes = [i32, i32, dbl, dbl, vp, vp, u64, u32, i32, i32]

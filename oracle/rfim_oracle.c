@@ -165,7 +165,9 @@ static void build_tables(orc_t *o) {
 orc_t *orc_create(int L, int R, double J, double h, const float *fields,
                   const double *temps, uint64_t seed, uint32_t realization,
                   int field_kind, int R_cap) {
-    if (L < 2 || L > 1024 || (L & 1)) { set_err("L must be even, 2..1024"); return NULL; }
+    /* L <= 512: the neighbour table alone takes 24 N bytes (3.2 GB at
+     * L = 512); larger lattices are replayed site by site in the tests */
+    if (L < 2 || L > 512 || (L & 1)) { set_err("L must be even, 2..512"); return NULL; }
     if (R_cap == 0) R_cap = R;
     if (R < 1 || R_cap < R) { set_err("need 1 <= R <= R_cap"); return NULL; }
     if (!fields || !temps) { set_err("null input"); return NULL; }

@@ -38,8 +38,9 @@ extern "C" {
 
 typedef struct orc orc_t;
 
-/* field_kind: -1 auto (bimodal iff every field is exactly +-1), 0 bimodal,
- * 1 continuous.  R_cap >= R bounds adaptive growth (0 means R). */
+/* L even, 2 <= L <= 512.  field_kind: -1 auto (bimodal iff every field is
+ * exactly +-1), 0 bimodal, 1 continuous.  R_cap >= R bounds adaptive growth
+ * (0 means R). */
 orc_t *orc_create(int L, int R, double J, double h, const float *fields,
                   const double *temps, uint64_t seed, uint32_t realization,
                   int field_kind, int R_cap);

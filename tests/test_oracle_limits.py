@@ -77,3 +77,18 @@ def test_ising_binder_crossing(oracle_mod):
     q = sign_change[0]
     Tc = temps[q] + (temps[q + 1] - temps[q]) * d[q] / (d[q] - d[q + 1])
     assert 4.42 <= Tc <= 4.62, (Tc, d)
+
+
+def test_oracle_rejects_lattices_it_cannot_hold(oracle_mod):
+    """The oracle accepts even L up to 512 (its neighbour table needs 24 L^3
+    bytes); larger L are refused before anything is read or allocated."""
+    import ctypes as C
+
+    lib = oracle_mod.lib()
+    f = np.ones(8, dtype=np.float32)
+    T = np.array([1.0])
+    for L in (514, 1024):
+        h = lib.orc_create(L, 1, 1.0, 1.0, f.ctypes.data_as(C.c_void_p), T.ctypes.data_as(C.c_void_p),
+                           0, 0, -1, 0)
+        assert not h
+        assert b"2..512" in lib.orc_last_error()
