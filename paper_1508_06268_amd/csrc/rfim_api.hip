@@ -68,7 +68,12 @@ hipError_t create_lane_stream(hipStream_t *s) {
 // The second stream of the two-stream sweeps, one per (device, handle
 // stream) and shared by every handle issuing on that stream, reference
 // counted.  Each call forks from and joins back into its handle stream, so
-// handles sharing a stream also share its order on the second stream.
+// handles sharing a stream also share its order on the second stream.  A
+// second stream that no handle holds any more stays alive and is bound to
+// the next handle stream on its device that needs one: a loop that creates
+// and destroys handles one at a time then reuses one hardware queue instead
+// of setting up a new one per handle.  Their number is the largest number
+// of handle streams in use at once on a device.
 struct SideStream {
     hipStream_t main;
     int device;
@@ -83,12 +88,22 @@ hipError_t acquire_side_stream(hipStream_t main, hipStream_t *side) {
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     std::lock_guard<std::mutex> lock(g_side_mu);
-    for (auto &s : g_side)
-        if (s.main == main && s.device == dev) {
+    SideStream *idle = nullptr;
+    for (auto &s : g_side) {
+        if (s.device != dev) continue;
+        if (s.main == main && s.refs > 0) {
             ++s.refs;
             *side = s.side;
             return hipSuccess;
         }
+        if (s.refs == 0 && (!idle || s.main == main)) idle = &s;
+    }
+    if (idle) {
+        idle->main = main;
+        idle->refs = 1;
+        *side = idle->side;
+        return hipSuccess;
+    }
     hipStream_t q = nullptr;
     if ((e = create_lane_stream(&q)) != hipSuccess) return e;
     g_side.push_back({main, dev, q, 1});
@@ -96,16 +111,15 @@ hipError_t acquire_side_stream(hipStream_t main, hipStream_t *side) {
     return hipSuccess;
 }
 
+// Drops one reference; the stream itself stays for reuse (every call that
+// forked work onto it has joined it back into its handle stream, which the
+// handle synchronizes before it lets go).
 void release_side_stream(hipStream_t side) {
     if (!side) return;
     std::lock_guard<std::mutex> lock(g_side_mu);
-    for (size_t i = 0; i < g_side.size(); ++i)
-        if (g_side[i].side == side) {
-            if (--g_side[i].refs == 0) {
-                (void)hipStreamSynchronize(side);
-                (void)hipStreamDestroy(side);
-                g_side.erase(g_side.begin() + (long)i);
-            }
+    for (auto &s : g_side)
+        if (s.side == side) {
+            if (s.refs > 0) --s.refs;
             return;
         }
 }
