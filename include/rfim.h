@@ -370,6 +370,35 @@ size_t rfim_pool_reserved(const rfim_pool_t *p);
 int rfim_pool_set_shape(rfim_pool_t *p, int L, int field_kind, int mode, int nw, int wg);
 int rfim_pool_synchronize(rfim_pool_t *p);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * per-replica energies E_r = -J B_r - h F_r of rfim_energies, computed from
+ * spin configurations and fields that the caller keeps on the device, with
+ * nothing allocated and nothing synchronized.
+ *   L           even, 2 <= L <= 1024.
+ *   R           1 <= R <= RFIM_NOALLOC_MAX_PARTIALS (2^18).
+ *   J, h        finite.
+ *   d_spins     device [R][L^3] int8, each +1 or -1, natural site order
+ *               i = x + L*(y + L*z) (the layout rfim_get_spins returns).
+ *   d_fields    device [L^3] float, natural site order.
+ *   d_E         device [R] double, written: E of configuration r.
+ *   hip_stream  hipStream_t of the current device (NULL: its null stream);
+ *               the work is queued there and the call returns at once.
+ * B counts each bond once (forward partners along x, y, z, periodic), as in
+ * rfim_energies; +-1 fields give the same values bit for bit, other fields
+ * agree to FP64 rounding (another summation order).  The partial sums live
+ * in a fixed 4 MiB device array of the library that every GPU it runs on
+ * holds until the process ends; it is shared by every call on that GPU, so
+ * calls that overlap on one GPU (two streams, two threads) race and must be
+ * ordered by the caller.  Errors: RFIM_EINVAL (bad argument), RFIM_ECAP
+ * (R too large), RFIM_EDEVICE (launch failure), all before any work is
+ * queued.
+ */
+#define RFIM_NOALLOC_MAX_PARTIALS (1 << 18)
+int rfim_energies_noalloc(int L, int R, double J, double h, const int8_t *d_spins, const float *d_fields,
+                          double *d_E, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

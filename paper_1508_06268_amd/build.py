@@ -18,7 +18,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "librfim.so")
-SOURCES = ["rfim_api.hip", "rfim_kernels.hip", "rfim_measure.hip"]
+SOURCES = ["rfim_api.hip", "rfim_kernels.hip", "rfim_measure.hip", "rfim_noalloc.hip"]
 HEADERS = [os.path.join(CSRC, "rfim_internal.h"), os.path.join(INCLUDE, "rfim.h")]
 ARCH = "gfx950"
 

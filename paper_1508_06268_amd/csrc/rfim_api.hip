@@ -126,6 +126,20 @@ void release_side_stream(hipStream_t side) {
 
 }  // namespace
 
+namespace rfim_host {
+
+int set_error(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+}  // namespace rfim_host
+
 struct rfim {
     // parameters
     int L = 0, N = 0, half = 0, R = 0, R_cap = 0, log2L = -1, kind = 0;

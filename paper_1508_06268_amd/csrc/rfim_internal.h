@@ -115,3 +115,8 @@ hipError_t launch_advance(const Lattice &lat, int tadv, hipStream_t s);
 hipError_t launch_fourier(const Lattice &lat, int32_t *part, const double *trig, double *fobs, hipStream_t s);
 
 }  // namespace rfim_dev
+
+namespace rfim_host {
+// Records a message for rfim_last_error() (printf-style) and returns code.
+int set_error(int code, const char *fmt, ...);
+}  // namespace rfim_host

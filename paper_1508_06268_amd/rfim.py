@@ -36,7 +36,9 @@ EXPORTS = [
     "rfim_pool_admit_job", "rfim_pool_step", "rfim_pool_poll", "rfim_pool_result",
     "rfim_pool_adapt", "rfim_pool_release", "rfim_pool_item",
     "rfim_pool_active", "rfim_pool_reserved", "rfim_pool_set_shape", "rfim_pool_synchronize",
+    "rfim_energies_noalloc",
 ]
+NOALLOC_MAX_PARTIALS = 1 << 18
 
 
 class RfimError(RuntimeError):
@@ -116,6 +118,7 @@ def load_library(path: str = LIB_PATH):
         "rfim_create_ex": (vp, [C.POINTER(rfim_params_t), C.POINTER(rfim_alloc_t), vp]),
         "rfim_sweep": (i32, [vp, i64, i32]),
         "rfim_energies": (i32, [vp, vp]),
+        "rfim_energies_noalloc": (i32, [i32, i32, dbl, dbl, vp, vp, vp, vp]),
         "rfim_adapt_temps": (i32, [vp, i32, i64, i32, dbl, i32, i32]),
         "rfim_destroy": (None, [vp]),
         "rfim_last_error": (C.c_char_p, []),
@@ -218,6 +221,23 @@ def rfim_energies(handle, R):
     E = np.zeros(R, dtype=np.float64)
     _check(load_library().rfim_energies(handle, _p(E)))
     return E
+
+
+def rfim_energies_noalloc(L, R, J, h, d_spins, d_fields, d_E, stream=None):
+    """Energies of R configurations held on the device, written to d_E on
+    `stream` without allocating or synchronizing.  d_spins (int8 [R][L^3],
+    +-1), d_fields (float32 [L^3]) and d_E (float64 [R]) are contiguous
+    torch tensors on the current device; stream a torch.cuda.Stream or None
+    (torch's current stream)."""
+    import torch
+
+    for t, dt, n in ((d_spins, torch.int8, R * L ** 3), (d_fields, torch.float32, L ** 3),
+                     (d_E, torch.float64, R)):
+        if not (t.is_cuda and t.dtype == dt and t.is_contiguous() and t.numel() == n):
+            raise ValueError("expected a contiguous %s device tensor of %d elements" % (dt, n))
+    s = (stream or torch.cuda.current_stream()).cuda_stream
+    _check(load_library().rfim_energies_noalloc(L, R, J, h, d_spins.data_ptr(), d_fields.data_ptr(),
+                                                d_E.data_ptr(), s))
 
 
 def rfim_adapt_temps(handle, trials, sweeps_per_trial, exchange_every, rate_threshold,

@@ -109,3 +109,18 @@ def test_pool_bytes_needed_accounts_every_buffer(rfim_mod, L, R, R_cap, kind):
     bad = W.Realization(L=L, R=R, J=1.0, h=1.0, fields=f, temps=W.linear_temps(R, 5.0, 1.0), seed=0,
                         sweeps=0, every=10, R_cap=R_cap)
     assert rfim_mod.Pool.bytes_needed(bad) == 0
+
+
+@pytest.mark.parametrize("L,R,J,ptr,code,msg", [
+    (7, 4, 1.0, 16, -1, "even"),
+    (8, 0, 1.0, 16, -1, "R must be"),
+    (8, (1 << 18) + 1, 1.0, 16, -5, "fixed partial array"),
+    (8, 4, 1.0, 0, -1, "NULL"),
+    (8, 4, float("nan"), 16, -1, "finite"),
+])
+def test_noalloc_energies_reject_bad_arguments(rfim_mod, L, R, J, ptr, code, msg):
+    """Validation happens before any device work (no GPU needed)."""
+    from paper_1508_06268_amd import rfim as B
+    lib = rfim_mod.load_library()
+    assert lib.rfim_energies_noalloc(L, R, J, 1.0, ptr, ptr, ptr, None) == code
+    assert msg in B.last_error()
