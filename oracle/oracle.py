@@ -101,6 +101,8 @@ def lib():
         L.orc_adapt_temps.restype = i32
         L.orc_insert_step.argtypes = [vp, dbl, i32, i32]
         L.orc_insert_step.restype = i32
+        L.orc_set_update_order.argtypes = [vp, i32, i32, i32, i32, i32]
+        L.orc_set_update_order.restype = i32
         L.orc_philox4x32_10.argtypes = [vp, vp, vp]
         L.orc_philox4x32_10.restype = None
         _lib = L
@@ -154,6 +156,11 @@ class Oracle:
         if rc < 0:
             raise RuntimeError(lib().orc_last_error().decode())
         return rc
+
+    def set_update_order(self, order, tiles=(0, 0, 0), hits=1):
+        """order 0: plain checkerboard; order 1: double checkerboard of
+        tiles (tx, ty, tz) with `hits` local sweeps per tile visit."""
+        self._check(lib().orc_set_update_order(self._h, int(order), *[int(t) for t in tiles], int(hits)))
 
     def sweep(self, n, every=0):
         self._check(lib().orc_sweep(self._h, int(n), int(every)))

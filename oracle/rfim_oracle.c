@@ -24,6 +24,11 @@
  *    tag 3, exchange step k:  ctr = (p, k, 0, .) for the pair (p, p+1),
  *                            U53 = ((w0 >> 11) * 2^32 + w1) * 2^-53.
  *
+ *  Double checkerboard with multi-hit updates (optional order, Sec. 3.2 and
+ *  Sec. 5.2; see tile_visits below): sweep t, local sweep (hit) m of a
+ *  tile visit, site of colour c: tag 2, ctr = (j >> 2, 2 (t hits + m) + c,
+ *  r, .), word j & 3 -- with hits = 1 the words of the plain sweep t.
+ *
  *  Metropolis (Sec. 2, Sec. 3.1 step 4; textbook rule min(1, e^{-b dE})).
  *    dE = 2 s_i (J n_i + h h_i), n_i = sum of the six neighbour spins.
  *    Bimodal fields: classes (a, b) = (s_i n_i, s_i h_i); a uint32 threshold
@@ -70,6 +75,9 @@ struct orc {
     uint64_t *att, *acc;    /* [R_cap] per lower slot of a pair */
     uint32_t *thr;          /* [R_cap][14] (bimodal) */
     uint8_t always[14];
+    /* update order: 0 plain two-colour checkerboard; 1 double checkerboard
+     * of tx * ty * tz tiles with `hits` local sweeps per tile visit */
+    int order, tx, ty, tz, hits;
 };
 
 static char g_err[256];
@@ -421,6 +429,66 @@ static void half_sweep(orc_t *o, int c) {
 }
 
 /* ------------------------------------------------------------------ */
+/* Double checkerboard with multi-hit updates (Sec. 3.2, Sec. 5.2)     */
+/* ------------------------------------------------------------------ */
+/* The lattice is cut into tiles of tx * ty * tz sites; tile (X, Y, Z) =  */
+/* (x / tx, y / ty, z / tz) has the coarse colour (X + Y + Z) mod 2.     */
+/* Sweep t visits every tile of coarse colour 0, then every tile of      */
+/* coarse colour 1 (the paper's two kernel executions per sweep).  A     */
+/* visited tile runs `hits` local sweeps of the fine checkerboard: its   */
+/* sites of colour 0, then its sites of colour 1 (Eq. 3), each the       */
+/* Metropolis update of the plain sweep.  With L / t_mu even, two tiles  */
+/* of one coarse colour never share a face, so every neighbour outside   */
+/* the visited tile lies in a tile of the other coarse colour and stays  */
+/* as it is while the tile runs.  Site i in hit m takes word j & 3 of    */
+/* the tag-2 block (j >> 2, 2 (t hits + m) + c(i), r).                   */
+static void tile_visits(orc_t *o, int coarse) {
+    const int L = o->L, Dx = L / o->tx, Dy = L / o->ty, Dz = L / o->tz;
+    for (int r = 0; r < o->R; ++r) {
+        int8_t *s = o->s + (size_t)r * o->N;
+        int slot = o->r2t[r];
+        for (int Z = 0; Z < Dz; ++Z)
+            for (int Y = 0; Y < Dy; ++Y)
+                for (int X = 0; X < Dx; ++X) {
+                    if (((X + Y + Z) & 1) != coarse) continue;
+                    for (int m = 0; m < o->hits; ++m) {
+                        uint32_t step = (uint32_t)(o->t * (uint64_t)o->hits + (uint64_t)m);
+                        for (int c = 0; c < 2; ++c)
+                            for (int z = Z * o->tz; z < (Z + 1) * o->tz; ++z)
+                                for (int y = Y * o->ty; y < (Y + 1) * o->ty; ++y)
+                                    for (int x = X * o->tx; x < (X + 1) * o->tx; ++x) {
+                                        int i = site_of(o, x, y, z);
+                                        if (colour(o, i) != c) continue;
+                                        int j = i >> 1;
+                                        uint32_t u = philox_word(o, TAG_SWEEP, (uint32_t)(j >> 2),
+                                                                 2u * step + (uint32_t)c, (uint32_t)r, j & 3);
+                                        if (accept_flip(o, s, i, slot, u)) s[i] = (int8_t)-s[i];
+                                    }
+                    }
+                }
+    }
+}
+
+int orc_set_update_order(orc_t *o, int order, int tx, int ty, int tz, int hits) {
+    if (order == 0) {
+        o->order = 0;
+        return 0;
+    }
+    if (order != 1) { set_err("order must be 0 (checkerboard) or 1 (tiles)"); return -1; }
+    const int L = o->L;
+    const int t[3] = {tx, ty, tz};
+    for (int d = 0; d < 3; ++d)
+        if (t[d] < 1 || L % t[d] != 0 || ((L / t[d]) & 1)) {
+            set_err("each tile side must divide L into an even number of tiles");
+            return -1;
+        }
+    if (hits < 1) { set_err("hits must be >= 1"); return -1; }
+    o->order = 1;
+    o->tx = tx; o->ty = ty; o->tz = tz; o->hits = hits;
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* Exchange (Eq. 2, temperatures swapped as in Sec. 3.3)               */
 /* ------------------------------------------------------------------ */
 int orc_exchange_once(orc_t *o) {
@@ -451,9 +519,18 @@ int orc_exchange_once(orc_t *o) {
 int orc_sweep(orc_t *o, int64_t n, int every) {
     if (n < 0 || every < 0) { set_err("n and every must be >= 0"); return -1; }
     if (o->t + (uint64_t)n > 0x7FFFFFFFull) { set_err("sweep counter limit 2^31-1"); return -5; }
+    if (o->order == 1 && (o->t + (uint64_t)n) * (uint64_t)o->hits > 0x80000000ull) {
+        set_err("sweep counter limit: (t + n) * hits must stay <= 2^31");
+        return -5;
+    }
     for (int64_t q = 0; q < n; ++q) {
-        half_sweep(o, 0);
-        half_sweep(o, 1);
+        if (o->order == 1) {
+            tile_visits(o, 0);
+            tile_visits(o, 1);
+        } else {
+            half_sweep(o, 0);
+            half_sweep(o, 1);
+        }
         o->t += 1;
         if (every > 0 && o->t % (uint64_t)every == 0) orc_exchange_once(o);
     }

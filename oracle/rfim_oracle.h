@@ -11,7 +11,9 @@
  *   - Hamiltonian H = -J sum_<ij> s_i s_j - h sum_i h_i s_i on a periodic L^3
  *     lattice, each bond counted once (Sec. 1, Eq. 1).
  *   - Checkerboard Metropolis: sites with (x+y+z) mod 2 = c are updated as
- *     one half-sweep, colour 0 then colour 1 (Sec. 2 and Sec. 3.2, Eq. 3).
+ *     one half-sweep, colour 0 then colour 1 (Sec. 2 and Sec. 3.2, Eq. 3);
+ *     optionally the double checkerboard of tiles with multi-hit local
+ *     sweeps (Sec. 3.2, Sec. 5.2).
  *   - Replica exchange between adjacent temperatures, odd/even alternation,
  *     acceptance min(1, e^Delta) with Delta = (b_{i+1}-b_i)(H(X_{i+1})-H(X_i))
  *     (Sec. 3.1, step 4, Eq. 2 -- printed with its cases swapped; the
@@ -53,6 +55,15 @@ int orc_field_kind(const orc_t *o);
 /* n sweeps; after a sweep that makes the global sweep count a multiple of
  * every (every > 0) an exchange step follows. */
 int orc_sweep(orc_t *o, int64_t n, int every);
+
+/* Update order of the sweeps.  order 0 (default): the plain two-colour
+ * checkerboard.  order 1: the double checkerboard with multi-hit updates
+ * (Sec. 3.2, Sec. 5.2): tiles of tx * ty * tz sites (each side dividing L
+ * into an even number of tiles) in a coarse checkerboard; each sweep visits
+ * the tiles of coarse colour 0, then those of colour 1, and each visit runs
+ * `hits` local two-colour sweeps of the tile.  Sweeps then need
+ * (t + n) * hits <= 2^31.  Returns 0 or -1. */
+int orc_set_update_order(orc_t *o, int order, int tx, int ty, int tz, int hits);
 
 /* Observables by temperature slot (ascending T). */
 int orc_energies(orc_t *o, double *E);
