@@ -234,6 +234,32 @@ int rfim_get_launch_shape(const rfim_t *h, int *mode, int *nw, int *wg);
 int rfim_set_concurrency(rfim_t *h, int streams);
 int rfim_get_concurrency(const rfim_t *h);
 
+/*
+ * Update order of the sweeps.  RFIM_ORDER_CHECKERBOARD (default): the plain
+ * two-colour checkerboard, sites with (x+y+z) mod 2 = 0 then the others
+ * (Sec. 3.2, Eq. 3), independent of launch shapes.  RFIM_ORDER_TILES: the
+ * double checkerboard with multi-hit updates (Sec. 3.2; the mh runs of
+ * Sec. 5.2): the lattice is cut into tiles of tx * ty * tz sites whose
+ * coarse colour is (x/tx + y/ty + z/tz) mod 2; each sweep visits the tiles
+ * of coarse colour 0, then those of colour 1, and each visit runs `hits`
+ * local sweeps of the tile (its colour-0 sites, then its colour-1 sites)
+ * while every site outside it stays as it is.  Hit m of sweep t draws the
+ * sweep words of plain sweep t*hits + m (tag 2, ctr = (j >> 2,
+ * 2(t*hits + m) + c, r)), so with hits = 1 only the order differs from the
+ * plain sweep.  The chain then depends on the tile shape.
+ *   Valid for power-of-two L >= 16: tx a multiple of 8; tx, ty, tz each
+ *   dividing L into an even number of tiles; (tx/8)*ty*tz a multiple of 64
+ *   in [64, 1024]; 1 <= hits <= 65536.  Sweeps need
+ *   (sweep counter + n) * hits <= 2^31 (RFIM_ECAP otherwise).
+ * Energies, exchanges and adaptive insertion are unchanged.  The order is
+ * not part of a checkpoint (set it again after rfim_load).  RFIM_ESTATE for
+ * batch and pool items (they sweep in the plain order).  Synchronizes.
+ */
+enum { RFIM_ORDER_CHECKERBOARD = 0, RFIM_ORDER_TILES = 1 };
+int rfim_set_update_order(rfim_t *h, int order, int tx, int ty, int tz, int hits);
+/* The current order; tx = ty = tz = 0 and hits = 1 for the plain order. */
+int rfim_get_update_order(const rfim_t *h, int *order, int *tx, int *ty, int *tz, int *hits);
+
 /* Checkpoint: the whole chain state (parameters, fields, temperatures,
  * spins, permutation, counters, exchange statistics) as a byte blob.
  * rfim_save with buf == NULL stores the needed size in *len.  A handle

@@ -160,6 +160,10 @@ struct rfim {
     hipStream_t aux_for = nullptr;  // the handle stream `aux` was acquired for
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int concurrency = 0;            // see rfim_set_concurrency
+    // update order: 0 plain checkerboard, 1 double checkerboard of tiles
+    // with multi-hit updates (rfim_set_update_order)
+    int order = 0;
+    rfim_dev::TileShape tiles = {0, 0, 0, 1};
     rfim_alloc_t alloc = {nullptr, nullptr, nullptr};   // device memory provider (rfim_create_ex)
     // optional Fourier measurement (rfim_set_measure)
     int measure = 0;
@@ -671,7 +675,8 @@ int sweep_impl(rfim *h, int64_t n, int every) {
     const rfim_dev::Launch ln = single_launch(h);
     const bool pow2 = h->log2L >= 3;
     const bool big = (long long)(h->R / 2) * h->half >= kSplitMinAttempts;
-    const bool split = pow2 && h->mode == 0 && h->R >= 2 &&
+    const bool tiled = h->order == 1;
+    const bool split = !tiled && pow2 && h->mode == 0 && h->R >= 2 &&
                        (h->concurrency == 2 || (h->concurrency == 0 && big));
     rfim_dev::Launch la = ln, lb = ln;
     if (split) {
@@ -702,8 +707,13 @@ int sweep_impl(rfim *h, int64_t n, int every) {
         int64_t to_next = every > 0 ? (int64_t)(every - (int64_t)(h->t % (uint64_t)every)) : remaining;
         const int m = (int)std::min<int64_t>(remaining, to_next);
         const bool exch = every > 0 && m == to_next;
-        const bool fused = exch && rfim_dev::fused_energy(lat);
-        if (pow2 && h->mode == 1) {
+        const bool fused = exch && !tiled && rfim_dev::fused_energy(lat);
+        if (tiled) {
+            for (int q = 0; q < m; ++q) {
+                HIPCHK(rfim_dev::launch_tile_sweep(lat, h->tiles, 0, q, h->stream));
+                HIPCHK(rfim_dev::launch_tile_sweep(lat, h->tiles, 1, q, h->stream));
+            }
+        } else if (pow2 && h->mode == 1) {
             HIPCHK(rfim_dev::launch_resident(ln, m, fused ? 1 : 0, h->stream));
         } else if (pow2 && split) {
             for (int q = 0; q < m; ++q) {
@@ -838,6 +848,8 @@ int rfim_sweep(rfim_t *h, int64_t n, int exchange_every) {
     if (h->in_batch) return fail(RFIM_ESTATE, "batch items advance through rfim_batch_sweep");
     if (n < 0 || exchange_every < 0) return fail(RFIM_EINVAL, "n and exchange_every must be >= 0");
     if (h->t + (uint64_t)n > kMaxSweeps) return fail(RFIM_ECAP, "global sweep counter would pass 2^31-1");
+    if (h->order == 1 && (h->t + (uint64_t)n) * (uint64_t)h->tiles.hits > (1ull << 31))
+        return fail(RFIM_ECAP, "tile order: (sweep counter + n) * hits would pass 2^31");
     return sweep_impl(h, n, exchange_every);
 }
 
@@ -1139,6 +1151,40 @@ int rfim_set_concurrency(rfim_t *h, int streams) {
 int rfim_get_concurrency(const rfim_t *h) {
     if (!h) return fail(RFIM_EINVAL, "handle is NULL");
     return h->concurrency;
+}
+
+int rfim_set_update_order(rfim_t *h, int order, int tx, int ty, int tz, int hits) {
+    if (!h) return fail(RFIM_EINVAL, "handle is NULL");
+    if (h->in_batch) return fail(RFIM_ESTATE, "batch and pool items sweep in the plain order");
+    if (order != RFIM_ORDER_CHECKERBOARD && order != RFIM_ORDER_TILES)
+        return fail(RFIM_EINVAL, "unknown update order %d", order);
+    if (order == RFIM_ORDER_TILES) {
+        const rfim_dev::TileShape ts = {tx, ty, tz, hits};
+        if (!rfim_dev::tile_shape_valid(h->L, ts))
+            return fail(RFIM_EINVAL,
+                        "tiles (%d, %d, %d) x %d hits not valid for L=%d: L a power of two >= 16, tx a multiple "
+                        "of 8, each side dividing L into an even number of tiles, (tx/8)*ty*tz a multiple of 64 "
+                        "in [64, 1024], 1 <= hits <= 65536",
+                        tx, ty, tz, hits, h->L);
+        if (h->t * (uint64_t)hits > (1ull << 31))
+            return fail(RFIM_ECAP, "tile order: sweep counter * hits would pass 2^31");
+        HIPCHK(hipStreamSynchronize(h->stream));
+        h->tiles = ts;
+    } else {
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    h->order = order;
+    return RFIM_OK;
+}
+
+int rfim_get_update_order(const rfim_t *h, int *order, int *tx, int *ty, int *tz, int *hits) {
+    if (!h || !order || !tx || !ty || !tz || !hits) return fail(RFIM_EINVAL, "NULL argument");
+    *order = h->order;
+    *tx = h->order ? h->tiles.tx : 0;
+    *ty = h->order ? h->tiles.ty : 0;
+    *tz = h->order ? h->tiles.tz : 0;
+    *hits = h->order ? h->tiles.hits : 1;
+    return RFIM_OK;
 }
 
 // ---- checkpoint ----------------------------------------------------

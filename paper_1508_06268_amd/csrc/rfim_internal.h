@@ -95,6 +95,20 @@ struct Launch {
     int r0 = 0;
 };
 
+// Double-checkerboard order with multi-hit updates (Sec. 3.2, Sec. 5.2):
+// tiles of tx * ty * tz sites, `hits` local sweeps per tile visit.  Valid
+// for L = 2^l >= 16 with tx a multiple of 8, every side dividing L into an
+// even number of tiles, (tx / 8) ty tz threads per workgroup in
+// {64, 128, ..., 1024}, the staged box within 64 KB of LDS, 1 <= hits <=
+// 65536.
+struct TileShape {
+    int tx, ty, tz, hits;
+};
+bool tile_shape_valid(int L, const TileShape &ts);
+size_t tile_lds_bytes(const TileShape &ts);
+// The tiles of coarse colour `coarse` of every replica at sweep t + toff.
+hipError_t launch_tile_sweep(const Lattice &lat, const TileShape &ts, int coarse, int toff, hipStream_t s);
+
 hipError_t launch_init(const Lattice &lat, int r0, int r1, hipStream_t s);
 // Streaming half-sweep of colour `colour` at sweep t + toff (power-of-two
 // L); energy != 0 on colour 1 also writes the energy partials.

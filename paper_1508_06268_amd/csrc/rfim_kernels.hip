@@ -657,6 +657,104 @@ __global__ __launch_bounds__(1024) void sweep_resident(Lattice lat0, const Latti
 }
 
 // ---------------------------------------------------------------------
+// Double checkerboard with multi-hit updates (Sec. 3.2, Sec. 5.2): one
+// workgroup per (replica, tile of the coarse colour), tile of tx * ty * tz
+// sites (tx a multiple of 8).  The tile and a one-site halo around it are
+// staged in LDS in the colour-split row layout of global memory: per colour
+// and per row (y, z) of the box (the tile's rows and one halo row on each
+// side in y and z), tx/2 bytes of the tile's sites with one dword before
+// (the left neighbour tile's last four sites of that colour) and one after
+// (the right neighbour's first four).  Every thread owns one dword (four
+// consecutive sites of a colour in a row) of each colour and runs `hits`
+// local sweeps -- its colour-0 dword, a barrier, its colour-1 dword, a
+// barrier -- with the same neighbour sums and decisions as the streaming
+// sweep; the halo is never written, so the neighbouring tiles stay frozen.
+// Hit m of sweep t draws the tag-2 block (j >> 2, 2 (t hits + m) + c, r).
+// Then the tile goes back to global memory.
+// ---------------------------------------------------------------------
+template <int KIND>
+__global__ __launch_bounds__(1024) void sweep_tiles(Lattice lat, TileShape ts, int coarse, int toff) {
+    extern __shared__ uint4 lds_raw[];
+    __shared__ uint32_t sthr[32];
+    uint8_t *box = (uint8_t *)lds_raw;
+    const uint32_t L = (uint32_t)lat.L, half = (uint32_t)lat.half;
+    const uint32_t tx = (uint32_t)ts.tx, ty = (uint32_t)ts.ty, tz = (uint32_t)ts.tz;
+    const uint32_t dwr = tx >> 3;                   // tile dwords per row and colour
+    const uint32_t rowb = 4u * (dwr + 2u);          // bytes per box row (with the halo dwords)
+    const uint32_t by = ty + 2u;
+    const uint32_t plane = rowb * by * (tz + 2u);   // bytes per colour
+    // block -> (replica, tile of the coarse colour)
+    const uint32_t dxh = L / tx / 2u, Dy = L / ty;
+    const uint32_t ntile = dxh * Dy * (L / tz);
+    const uint32_t r = blockIdx.x / ntile, q = blockIdx.x % ntile;
+    const uint32_t Y = (q / dxh) % Dy, Z = q / (dxh * Dy);
+    const uint32_t X = 2u * (q % dxh) + (((uint32_t)coarse + Y + Z) & 1u);
+    const uint32_t x0 = X * tx, y0 = Y * ty, z0 = Z * tz;
+    GAS uint8_t *spins = gptr(lat.spins) + (size_t)r * lat.N;
+    const int slot = gptr(lat.r2t)[r];
+    if (KIND == 0 && threadIdx.x < 32u) sthr[threadIdx.x] = gptr(lat.thr)[slot * 32 + threadIdx.x];
+    const float beta = KIND == 1 ? gptr(lat.betaf)[slot] : 0.0f;
+    const uint32_t t = (uint32_t)(gptr(lat.ctrs)[0] + (uint64_t)toff);
+    // stage the box: both colours, every row of the box, the tile's dwords
+    // and the two halo dwords (x, y, z wrap around the periodic lattice)
+    const uint32_t nbox = 2u * (dwr + 2u) * by * (tz + 2u);
+    for (uint32_t e = threadIdx.x; e < nbox; e += blockDim.x) {
+        const uint32_t d = e % (dwr + 2u), row = (e / (dwr + 2u)) % (by * (tz + 2u));
+        const uint32_t c = e / ((dwr + 2u) * by * (tz + 2u));
+        const uint32_t yy = row % by, zz = row / by;
+        const uint32_t x = (x0 + L + 8u * d - 8u) & (L - 1u);
+        const uint32_t y = (y0 + L + yy - 1u) & (L - 1u), z = (z0 + L + zz - 1u) & (L - 1u);
+        const uint32_t j = (x + L * (y + L * z)) >> 1;
+        *(uint32_t *)(box + c * plane + row * rowb + 4u * d) =
+            *(GAS const uint32_t *)(spins + (size_t)c * half + j);
+    }
+    // this thread's dword: four sites of row (y0 + yy, z0 + zz) from
+    // x0 + 8w, in each colour
+    const uint32_t w = threadIdx.x % dwr, yy = (threadIdx.x / dwr) % ty, zz = threadIdx.x / (dwr * ty);
+    const uint32_t j0 = (x0 + 8u * w + L * ((y0 + yy) + L * (z0 + zz))) >> 1;
+    const uint32_t g0 = j0 >> 2;
+    const uint32_t mid = ((zz + 1u) * by + (yy + 1u)) * rowb + 4u * (w + 1u);
+    uint32_t F4[2][1] = {{0u}, {0u}};
+    f32x4 HF[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        if (KIND == 0) {
+            F4[c][0] = *(GAS const uint32_t *)(gptr(lat.fbits) + (size_t)c * half + j0);
+        } else {
+            HF[c] = *(GAS const f32x4 *)(gptr(lat.fhf) + (size_t)c * half + j0);
+        }
+    }
+    __syncthreads();
+    const uint32_t never = KIND == 0 ? __builtin_amdgcn_readfirstlane(sthr[31]) : 0u;
+    const uint32_t p0 = (y0 + yy + z0 + zz) & 1u;   // (c + y + z) & 1 for colour 0
+    for (int m = 0; m < ts.hits; ++m) {
+        const uint32_t step = t * (uint32_t)ts.hits + (uint32_t)m;
+#pragma unroll
+        for (uint32_t c = 0; c < 2; ++c) {
+            const uint8_t *oth = box + (1u - c) * plane;
+            ChunkIn<KIND, 1> in;
+            in.c.p = p0 ^ c;
+            in.Wown[0] = *(const uint32_t *)(box + c * plane + mid);
+            in.a.W[0] = *(const uint32_t *)(oth + mid);
+            in.a.Wx = *(const uint32_t *)(oth + mid + (in.c.p ? 4u : 0u - 4u));
+            in.a.Wyp[0] = *(const uint32_t *)(oth + mid + rowb);
+            in.a.Wym[0] = *(const uint32_t *)(oth + mid - rowb);
+            in.a.Wzp[0] = *(const uint32_t *)(oth + mid + rowb * by);
+            in.a.Wzm[0] = *(const uint32_t *)(oth + mid - rowb * by);
+            if (KIND == 1) in.HF[0] = HF[c];
+            uint32_t Wn[1], Un[1], Wnew[1];
+            const uint32_t any = chunk_flip_any<KIND, 1>(lat, sthr, never, in, F4[c], g0, 2u * step + c, r, beta,
+                                                         Wn, Un, Wnew);
+            if (any) *(uint32_t *)(box + c * plane + mid) = Wnew[0];
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (uint32_t c = 0; c < 2; ++c)
+        *(GAS uint32_t *)(spins + (size_t)c * half + j0) = *(const uint32_t *)(box + c * plane + mid);
+}
+
+// ---------------------------------------------------------------------
 // Energy partials (Eq. 1).  Every bond joins a colour-0 and a colour-1
 // site, so B = sum over colour-1 sites of s_i n_i counts each bond once;
 // F and M run over both colours.  Grid (nblk, R); fixed reduction order.
@@ -1044,6 +1142,32 @@ hipError_t launch_generic_sweep(const Lattice &lat, int colour, int toff, hipStr
         hipLaunchKernelGGL(sweep_generic<0>, grid, dim3(256), 0, s, lat, colour, toff);
     else
         hipLaunchKernelGGL(sweep_generic<1>, grid, dim3(256), 0, s, lat, colour, toff);
+    return hipGetLastError();
+}
+
+bool tile_shape_valid(int L, const TileShape &ts) {
+    if (L < 16 || L > 1024 || (L & (L - 1))) return false;
+    const int t[3] = {ts.tx, ts.ty, ts.tz};
+    for (int d = 0; d < 3; ++d)
+        if (t[d] < 1 || L % t[d] != 0 || ((L / t[d]) & 1)) return false;
+    if (ts.tx % 8 != 0) return false;
+    const long long threads = (long long)(ts.tx / 8) * ts.ty * ts.tz;
+    if (threads < 64 || threads > 1024 || threads % 64 != 0) return false;
+    if (tile_lds_bytes(ts) > 65536) return false;
+    return ts.hits >= 1 && ts.hits <= 65536;
+}
+
+size_t tile_lds_bytes(const TileShape &ts) {
+    return 2u * (size_t)(4 * (ts.tx / 8 + 2)) * (size_t)(ts.ty + 2) * (size_t)(ts.tz + 2);
+}
+
+hipError_t launch_tile_sweep(const Lattice &lat, const TileShape &ts, int coarse, int toff, hipStream_t s) {
+    const int ntile = (lat.L / ts.tx) * (lat.L / ts.ty) * (lat.L / ts.tz) / 2;
+    const dim3 grid((unsigned)(ntile * lat.R)), block((unsigned)((ts.tx / 8) * ts.ty * ts.tz));
+    if (lat.kind == 0)
+        hipLaunchKernelGGL(sweep_tiles<0>, grid, block, tile_lds_bytes(ts), s, lat, ts, coarse, toff);
+    else
+        hipLaunchKernelGGL(sweep_tiles<1>, grid, block, tile_lds_bytes(ts), s, lat, ts, coarse, toff);
     return hipGetLastError();
 }
 

@@ -36,8 +36,9 @@ EXPORTS = [
     "rfim_pool_admit_job", "rfim_pool_step", "rfim_pool_poll", "rfim_pool_result",
     "rfim_pool_adapt", "rfim_pool_release", "rfim_pool_item",
     "rfim_pool_active", "rfim_pool_reserved", "rfim_pool_set_shape", "rfim_pool_synchronize",
-    "rfim_energies_noalloc",
+    "rfim_energies_noalloc", "rfim_set_update_order", "rfim_get_update_order",
 ]
+ORDER_CHECKERBOARD, ORDER_TILES = 0, 1
 NOALLOC_MAX_PARTIALS = 1 << 18
 
 
@@ -119,6 +120,8 @@ def load_library(path: str = LIB_PATH):
         "rfim_sweep": (i32, [vp, i64, i32]),
         "rfim_energies": (i32, [vp, vp]),
         "rfim_energies_noalloc": (i32, [i32, i32, dbl, dbl, vp, vp, vp, vp]),
+        "rfim_set_update_order": (i32, [vp, i32, i32, i32, i32, i32]),
+        "rfim_get_update_order": (i32, [vp, vp, vp, vp, vp, vp]),
         "rfim_adapt_temps": (i32, [vp, i32, i64, i32, dbl, i32, i32]),
         "rfim_destroy": (None, [vp]),
         "rfim_last_error": (C.c_char_p, []),
@@ -414,6 +417,18 @@ class Rfim:
     def set_concurrency(self, streams: int):
         """0 automatic, 1 one stream, 2 two streams (see rfim_set_concurrency)."""
         _check(load_library().rfim_set_concurrency(self._h, int(streams)))
+
+    def set_update_order(self, order: int, tiles=(0, 0, 0), hits: int = 1):
+        """ORDER_CHECKERBOARD, or ORDER_TILES with tiles (tx, ty, tz) and
+        `hits` local sweeps per tile visit (see rfim_set_update_order)."""
+        tx, ty, tz = (int(v) for v in tiles)
+        _check(load_library().rfim_set_update_order(self._h, int(order), tx, ty, tz, int(hits)))
+
+    def update_order(self):
+        """(order, (tx, ty, tz), hits)."""
+        v = [C.c_int(0) for _ in range(5)]
+        _check(load_library().rfim_get_update_order(self._h, *[C.byref(x) for x in v]))
+        return v[0].value, (v[1].value, v[2].value, v[3].value), v[4].value
 
     def save(self) -> bytes:
         n = C.c_size_t(0)
