@@ -387,6 +387,37 @@ def paper_scale_leg(torch, P, W, reps=3):
             "bytes_per_attempt_shared_field": round(bpa, 4)}
 
 
+def multi_hit_leg(torch, P, W, hits=100, tiles=(32, 8, 8), sweeps=4, reps=5):
+    """The double-checkerboard order with multi-hit updates (Sec. 3.2; the
+    mh = 100 runs of Sec. 5.2) on the L=64 workload's realization at its
+    production size (R=192, +-1 fields h=2.25): `hits` local sweeps per tile
+    visit, tiles staged in LDS.  Median of `reps` event-timed runs of
+    `sweeps` sweeps with an exchange every 2."""
+    w = W.adaptive_l64()
+    stream = torch.cuda.Stream()
+    h = P.Rfim(w.L, w.R_cap, w.J, w.h, w.fields, W.linear_temps(w.R_cap, 1.0, 6.0), seed=w.seed, stream=stream)
+    h.set_update_order(P.rfim.ORDER_TILES, tiles, hits)
+    h.sweep(2, 2)
+    h.synchronize()
+    times = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        h.sweep(sweeps, 2)
+        e1.record(stream)
+        stream.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+    h.close()
+    dt = float(np.median(times))
+    attempts = w.R_cap * w.L ** 3 * hits * sweeps
+    rate = attempts / dt / 1e9
+    log("multi-hit: L=64 R=%d tiles %s, %d hits: %.1f attempts/ns" % (w.R_cap, tiles, hits, rate))
+    return {"workload": "multi_hit_l64", "L": w.L, "R": w.R_cap, "fields": "bimodal +-1", "h": w.h,
+            "tiles": list(tiles), "hits": hits, "sweeps": sweeps, "exchange_every": 2, "reps": reps,
+            "seconds": round(dt, 6), "attempts_per_ns": round(rate, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -544,6 +575,9 @@ def main():
     paper_scale = paper_scale_leg(torch, P, W)
     batched = None if args.no_batched else batched_leg(torch, P, W)
     served = None if args.no_served else served_leg(torch, P, W)
+    # last of the GPU legs: its sustained VALU load can lower the clock for
+    # what follows
+    multi_hit = multi_hit_leg(torch, P, W)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -574,6 +608,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "paper_scale_l32": paper_scale,
+        "multi_hit_l64": multi_hit,
         "batched": batched,
         "served": served,
     }
