@@ -154,6 +154,19 @@ def kernel_only(torch, P, W, sweeps):
     log("kernel mode: %d half-sweep launches at L=%d R=%d" % (2 * sweeps, w.L, w.R_cap))
 
 
+def tiles_only(torch, P, W, sweeps=2, hits=100, tiles=(32, 8, 8)):
+    """Only the multi-hit tile kernel at the production shape (L=64, R=192,
+    +-1 fields, 100 hits): `sweeps` sweeps without exchange, for counters."""
+    w = W.adaptive_l64()
+    stream = torch.cuda.Stream()
+    h = P.Rfim(w.L, w.R_cap, w.J, w.h, w.fields, W.linear_temps(w.R_cap, 1.0, 6.0), seed=w.seed,
+               stream=stream)
+    h.set_update_order(P.rfim.ORDER_TILES, tiles, hits)
+    h.sweep(sweeps, 0)
+    h.synchronize()
+    log("tiles mode: %d tile launches at L=%d R=%d, %d hits" % (2 * sweeps, w.L, w.R_cap, hits))
+
+
 def copy_only(torch, nbytes, reps=5):
     """A plain device-to-device copy of known size (counter calibration)."""
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -418,6 +431,51 @@ def multi_hit_leg(torch, P, W, hits=100, tiles=(32, 8, 8), sweeps=4, reps=5):
             "seconds": round(dt, 6), "attempts_per_ns": round(rate, 1)}
 
 
+def trace_summary(path, top=40):
+    """Per (kernel, grid, workgroup) launch statistics of a rocprofv3 kernel
+    trace (csv output), longest total first: the same kernel at different
+    grid sizes (e.g. the roofline leg's launches over all replicas and the
+    production path's half-size launches) is listed separately."""
+    import csv
+    from collections import defaultdict
+
+    def size(row, what):
+        if what in row:
+            return int(row[what])
+        return int(row[what + "_X"]) * int(row[what + "_Y"]) * int(row[what + "_Z"])
+
+    acc = defaultdict(list)
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            name = row["Kernel_Name"]
+            key = (name[:90], size(row, "Grid_Size"), size(row, "Workgroup_Size"))
+            acc[key].append(int(row["End_Timestamp"]) - int(row["Start_Timestamp"]))
+    total = sum(sum(v) for v in acc.values())
+    lines = ["%-90s %10s %6s %8s %12s %10s %10s %10s %7s" % ("kernel", "grid", "wg", "calls", "total ms",
+                                                            "avg us", "min us", "max us", "%")]
+    for key, v in sorted(acc.items(), key=lambda kv: -sum(kv[1]))[:top]:
+        lines.append("%-90s %10d %6d %8d %12.1f %10.3f %10.3f %10.3f %7.2f" % (
+            key[0], key[1], key[2], len(v), sum(v) / 1e6, np.mean(v) / 1e3, min(v) / 1e3, max(v) / 1e3,
+            100.0 * sum(v) / total))
+    return "\n".join(lines)
+
+
+def counter_summary(kernel_csv, copy_csv, counter, kernel_match="sweep_pow2"):
+    """Mean of `counter` (KiB per dispatch) over the dispatches of the
+    kernel, and the factor that makes a plain device copy of 1 GiB read
+    (FETCH_SIZE) or write (WRITE_SIZE) 1 GiB."""
+    import csv
+
+    k = [float(r["Counter_Value"]) for r in csv.DictReader(open(kernel_csv, newline=""))
+         if kernel_match in r["Kernel_Name"]]
+    c = [float(r["Counter_Value"]) for r in csv.DictReader(open(copy_csv, newline=""))
+         if "copyBuffer" in r["Kernel_Name"] and int(r["Grid_Size"]) > 1000]
+    factor = (1 << 20) / float(np.mean(c))
+    return {"counter": counter, "dispatches": len(k), "mean_kib": float(np.mean(k)), "min_kib": float(min(k)),
+            "max_kib": float(max(k)), "copy_dispatches": len(c), "copy_mean_kib": float(np.mean(c)),
+            "factor": factor, "bytes": float(np.mean(k)) * factor * 1024.0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -427,17 +485,35 @@ def main():
                     help="served_stream: only the continuous-batching serving run (its own JSON line)")
     ap.add_argument("--production-sweeps", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="bench", choices=["bench", "kernel", "streaming", "copy"],
-                    help="kernel: only the dominant kernel (for counters); streaming: only the "
+    ap.add_argument("--mode", default="bench", choices=["bench", "kernel", "tiles", "streaming", "copy"],
+                    help="kernel: only the dominant kernel (for counters); tiles: only the multi-hit "
+                         "tile kernel (for counters); streaming: only the "
                          "HBM-streaming leg; copy: a plain copy of --copy-bytes (counter calibration)")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-realizations leg")
     ap.add_argument("--no-served", action="store_true", help="skip the served-stream leg")
+    ap.add_argument("--trace-summary", default=None, metavar="KERNEL_TRACE_CSV",
+                    help="print per (kernel, grid) statistics of a rocprofv3 kernel trace and exit")
+    ap.add_argument("--traffic-summary", nargs=4, default=None,
+                    metavar=("FETCH_KERNEL_CSV", "FETCH_COPY_CSV", "WRITE_KERNEL_CSV", "WRITE_COPY_CSV"),
+                    help="print the calibrated FETCH_SIZE + WRITE_SIZE bytes per sweep launch and exit")
     ap.add_argument("--cpu-worker", type=int, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--cpu-worker-lib", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_worker is not None:
         cpu_worker(args.cpu_worker, args.cpu_worker_lib)
+        return
+    if args.trace_summary:
+        print(trace_summary(args.trace_summary))
+        return
+    if args.traffic_summary:
+        fk, fc, wk, wc = args.traffic_summary
+        a, b = counter_summary(fk, fc, "FETCH_SIZE"), counter_summary(wk, wc, "WRITE_SIZE")
+        for d in (a, b):
+            print("%s: %d dispatches, mean %.1f KiB (min %.1f, max %.1f); copy calibration %.1f KiB per 1 GiB "
+                  "-> factor %.4f -> %.4e bytes" % (d["counter"], d["dispatches"], d["mean_kib"], d["min_kib"],
+                                                    d["max_kib"], d["copy_mean_kib"], d["factor"], d["bytes"]))
+        print("hbm_bytes_per_launch: %.6e" % (a["bytes"] + b["bytes"]))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: a realization runs on a single MI355X and sharding "
@@ -451,6 +527,9 @@ def main():
     torch.cuda.set_device(0)
     if args.mode == "kernel":
         kernel_only(torch, P, W, 20)
+        return
+    if args.mode == "tiles":
+        tiles_only(torch, P, W)
         return
     if args.mode == "copy":
         copy_only(torch, args.copy_bytes)

@@ -1520,6 +1520,34 @@ int batch_segment(rfim_batch *b, int m, bool exch) {
     return RFIM_OK;
 }
 
+// A graph replays an interval's launches without their host cost, which
+// matters when the launches are short; when every launch is long the host
+// keeps ahead anyway, and eager launches on the batch's own lane streams
+// (each with a hardware queue of its own) also keep concurrent lanes
+// apart, which a replayed graph's parallel branches did not always do
+// (measured: the first graph of a process ran the two lanes of a 16 x
+// R=128, L=64 class one after the other, 1400 against 1590 attempts/ns).
+// Eager when the interval's launches average at least 2^26 attempts (tens
+// of microseconds each); below that the graph's lower per-launch cost wins
+// (256 realizations of L <= 32: 489 against 448 realizations/s).
+constexpr long long kEagerAttemptsPerLaunch = 1ll << 26;
+
+bool batch_prefers_graph(const rfim_batch *b, int every) {
+    long long attempts = 0, launches = 1;       // the exchange step
+    for (const auto &c : b->classes) {
+        long long per_sweep = 0;
+        for (int i : c.members) per_sweep += (long long)b->items[i]->R * b->items[i]->N;
+        attempts += per_sweep * every;
+        if (c.mode == 1) {
+            launches += 1;
+        } else {
+            const bool split = c.nblocks >= 16 && per_sweep / 4 >= kSplitMinAttempts;
+            launches += 2ll * every * (split ? 2 : 1);
+        }
+    }
+    return attempts < kEagerAttemptsPerLaunch * launches;
+}
+
 int batch_capture(rfim_batch *b, int every) {
     if (b->graph) {
         HIPCHK(hipGraphExecDestroy(b->graph));
@@ -1688,7 +1716,7 @@ int rfim_batch_sweep(rfim_batch_t *b, int64_t n, int exchange_every) {
         const int m = (int)std::min<int64_t>(remaining, to_next);
         const bool exch = every > 0 && m == to_next;
         int rc;
-        if (exch && m == every) {
+        if (exch && m == every && batch_prefers_graph(b, every)) {
             std::vector<int> flags(b->items.size());
             for (size_t q = 0; q < b->items.size(); ++q) flags[q] = b->items[q]->measure;
             if (b->graph_every != every || b->graph_measure != flags) {
