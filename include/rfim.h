@@ -255,6 +255,29 @@ int rfim_get_concurrency(const rfim_t *h);
  * not part of a checkpoint (set it again after rfim_load).  RFIM_ESTATE for
  * batch and pool items (they sweep in the plain order).  Synchronizes.
  */
+/*
+ * Spin storage.  RFIM_SPINS_BYTES: one byte per spin.  RFIM_SPINS_BITS:
+ * one bit per spin (multi-spin coding): per replica and colour, N/64 words
+ * of 32 same-colour sites; the sweep forms neighbour counts with a
+ * bit-sliced adder and takes the same decisions with the same random words,
+ * so the chain is unchanged, with 1/8 of the bytes per spin-flip attempt.
+ * Bits are valid for L = 64, 128 or 256 in the plain checkerboard order
+ * without the Fourier measurement (RFIM_EINVAL / RFIM_ESTATE otherwise,
+ * RFIM_ENOMEM if the bit arrays, R_cap * L^3 / 8 bytes plus L^3 / 8 for
+ * +-1 fields, allocated on first use, cannot be had).  A handle made by
+ * rfim_create / rfim_create_ex / rfim_load with +-1 fields at L = 64..256
+ * starts in bits, every other handle in bytes; rfim_set_launch_shape (its
+ * shapes are the byte kernels'), rfim_set_measure with the Fourier flag and
+ * rfim_set_update_order with tiles switch a handle to bytes.  Calls that
+ * read or write spins (energies, spins, checkpoints, adaptive insertion)
+ * work in either storage.  RFIM_ESTATE for batch and pool items (bytes).
+ * Asynchronous on the handle's stream.
+ */
+enum { RFIM_SPINS_BYTES = 0, RFIM_SPINS_BITS = 1 };
+int rfim_set_spin_storage(rfim_t *h, int storage);
+/* RFIM_SPINS_BYTES or RFIM_SPINS_BITS. */
+int rfim_get_spin_storage(const rfim_t *h);
+
 enum { RFIM_ORDER_CHECKERBOARD = 0, RFIM_ORDER_TILES = 1 };
 int rfim_set_update_order(rfim_t *h, int order, int tx, int ty, int tz, int hits);
 /* The current order; tx = ty = tz = 0 and hits = 1 for the plain order. */

@@ -164,6 +164,11 @@ struct rfim {
     // with multi-hit updates (rfim_set_update_order)
     int order = 0;
     rfim_dev::TileShape tiles = {0, 0, 0, 1};
+    // spin storage: bytes in d_spins, or one bit per spin in d_bits
+    // (rfim_set_spin_storage; the byte array is then a mirror brought up to
+    // date before any call that reads it)
+    bool bits_mode = false;
+    uint32_t *d_bits = nullptr, *d_fbw = nullptr;
     rfim_alloc_t alloc = {nullptr, nullptr, nullptr};   // device memory provider (rfim_create_ex)
     // optional Fourier measurement (rfim_set_measure)
     int measure = 0;
@@ -225,6 +230,8 @@ struct rfim {
         a.E = d_E;
         a.Mr = d_Mr;
         a.obs = d_obs;
+        a.bits = bits_mode ? d_bits : nullptr;
+        a.fbw = d_fbw;
         return a;
     }
 };
@@ -260,6 +267,8 @@ void free_device(rfim *h) {
     dev_free(h, h->d_fpart);
     dev_free(h, h->d_trig);
     dev_free(h, h->d_fobs);
+    dev_free(h, (void *)h->d_bits);
+    dev_free(h, (void *)h->d_fbw);
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);
     release_side_stream(h->aux);
@@ -549,7 +558,21 @@ int download_perm(rfim *h, std::vector<int32_t> &t2r) {
     return RFIM_OK;
 }
 
+// Bit storage: bring the byte array up to date before code that reads it,
+// and the bits after code that wrote it.
+int bytes_from_bits(rfim *h) {
+    if (h->bits_mode) HIPCHK(rfim_dev::launch_unpack_bits(h->lattice(), h->stream));
+    return RFIM_OK;
+}
+
+int bits_from_bytes(rfim *h) {
+    if (h->bits_mode) HIPCHK(rfim_dev::launch_pack_bits(h->lattice(), h->stream));
+    return RFIM_OK;
+}
+
 int compute_components(rfim *h) {
+    int rc;
+    if ((rc = bytes_from_bits(h))) return rc;
     Lattice lat = h->lattice();
     HIPCHK(rfim_dev::launch_energy(lat, h->stream));
     HIPCHK(rfim_dev::launch_reduce(lat, h->d_B, h->d_F, h->d_M, h->stream));
@@ -676,17 +699,20 @@ int sweep_impl(rfim *h, int64_t n, int every) {
     const bool pow2 = h->log2L >= 3;
     const bool big = (long long)(h->R / 2) * h->half >= kSplitMinAttempts;
     const bool tiled = h->order == 1;
-    const bool split = !tiled && pow2 && h->mode == 0 && h->R >= 2 &&
+    const bool bitsm = h->bits_mode;
+    const bool split = !tiled && pow2 && (bitsm || h->mode == 0) && h->R >= 2 &&
                        (h->concurrency == 2 || (h->concurrency == 0 && big));
     rfim_dev::Launch la = ln, lb = ln;
+    const int ra = split ? h->R / 2 : h->R;
     if (split) {
         int rc;
         if ((rc = ensure_aux(h))) return rc;
-        const int wpr = ln.nblocks / h->R;
-        const int ra = h->R / 2;
-        la.nblocks = ra * wpr;
-        lb.r0 = ra;
-        lb.nblocks = (h->R - ra) * wpr;
+        if (!bitsm) {
+            const int wpr = ln.nblocks / h->R;
+            la.nblocks = ra * wpr;
+            lb.r0 = ra;
+            lb.nblocks = (h->R - ra) * wpr;
+        }
     }
     // Two streams: one fork at the start of the call and one join at its
     // end.  At each exchange step the streams meet once: the stream running
@@ -707,8 +733,16 @@ int sweep_impl(rfim *h, int64_t n, int every) {
         int64_t to_next = every > 0 ? (int64_t)(every - (int64_t)(h->t % (uint64_t)every)) : remaining;
         const int m = (int)std::min<int64_t>(remaining, to_next);
         const bool exch = every > 0 && m == to_next;
-        const bool fused = exch && !tiled && rfim_dev::fused_energy(lat);
-        if (tiled) {
+        const bool fused = exch && !tiled && (bitsm || rfim_dev::fused_energy(lat));
+        if (bitsm) {
+            for (int q = 0; q < m; ++q) {
+                const int e = fused && q == m - 1;
+                HIPCHK(rfim_dev::launch_bits_sweep(lat, 0, ra, 0, q, 0, h->stream));
+                if (split) HIPCHK(rfim_dev::launch_bits_sweep(lat, ra, h->R - ra, 0, q, 0, h->aux));
+                HIPCHK(rfim_dev::launch_bits_sweep(lat, 0, ra, 1, q, e, h->stream));
+                if (split) HIPCHK(rfim_dev::launch_bits_sweep(lat, ra, h->R - ra, 1, q, e, h->aux));
+            }
+        } else if (tiled) {
             for (int q = 0; q < m; ++q) {
                 HIPCHK(rfim_dev::launch_tile_sweep(lat, h->tiles, 0, q, h->stream));
                 HIPCHK(rfim_dev::launch_tile_sweep(lat, h->tiles, 1, q, h->stream));
@@ -795,6 +829,13 @@ rfim_t *rfim_create_ex(const rfim_params_t *params, const rfim_alloc_t *alloc, v
         destroy_impl(h);
         g_error = msg;
         return nullptr;
+    }
+    // +-1 fields at L = 64..256 default to one bit per spin, the faster
+    // storage there (the same chain); if its arrays cannot be had the
+    // handle keeps byte spins
+    if (h->kind == 0 && rfim_dev::bits_valid(h->L) && rfim_set_spin_storage(h, RFIM_SPINS_BITS) != RFIM_OK) {
+        (void)hipGetLastError();
+        g_error.clear();
     }
     return h;
 }
@@ -902,6 +943,8 @@ int rfim_get_spins(rfim_t *h, int8_t *s) {
     if (!h || !s) return fail(RFIM_EINVAL, "NULL argument");
     const size_t N = (size_t)h->N, half = N / 2;
     std::vector<uint8_t> dev((size_t)h->R * N);
+    int rc;
+    if ((rc = bytes_from_bits(h))) return rc;
     HIPCHK(hipMemcpyAsync(dev.data(), h->d_spins, dev.size(), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     for (int r = 0; r < h->R; ++r) {
@@ -924,6 +967,8 @@ int rfim_set_spins(rfim_t *h, const int8_t *s) {
         for_each_site(h->L, [&](size_t i, int c, size_t j) { dst[c * half + j] = src[i] > 0 ? 1 : 0; });
     }
     HIPCHK(hipMemcpyAsync(h->d_spins, dev.data(), dev.size(), hipMemcpyHostToDevice, h->stream));
+    int rc;
+    if ((rc = bits_from_bytes(h))) return rc;
     HIPCHK(hipStreamSynchronize(h->stream));
     return RFIM_OK;
 }
@@ -1019,8 +1064,14 @@ static int insert_step(rfim *h, double rate_threshold, int max_insert, int R_cap
         const int p = picked[q];
         const int32_t id = R0 + (int32_t)q;
         slots.push_back({(h->T[p] + h->T[p + 1]) / 2.0, id});
-        HIPCHK(hipMemcpyAsync(h->d_spins + (size_t)id * h->N, h->d_spins + (size_t)t2r[p] * h->N,
-                              (size_t)h->N, hipMemcpyDeviceToDevice, h->stream));
+        if (h->bits_mode) {
+            const size_t words = (size_t)h->N / 32;     // both colours of one replica
+            HIPCHK(hipMemcpyAsync(h->d_bits + (size_t)id * words, h->d_bits + (size_t)t2r[p] * words,
+                                  words * 4, hipMemcpyDeviceToDevice, h->stream));
+        } else {
+            HIPCHK(hipMemcpyAsync(h->d_spins + (size_t)id * h->N, h->d_spins + (size_t)t2r[p] * h->N,
+                                  (size_t)h->N, hipMemcpyDeviceToDevice, h->stream));
+        }
     }
     std::sort(slots.begin(), slots.end(),
               [](const std::pair<double, int32_t> &a, const std::pair<double, int32_t> &b) {
@@ -1080,6 +1131,8 @@ int rfim_set_launch_shape(rfim_t *h, int mode, int nw, int wg) {
     if (h->in_batch) return fail(RFIM_ESTATE, "batch items take their class shape (rfim_batch_set_shape)");
     if (!rfim_dev::shape_valid(h->L, mode, nw, wg))
         return fail(RFIM_EINVAL, "launch shape (%d, %d, %d) not valid for L=%d", mode, nw, wg, h->L);
+    int rc;
+    if (h->bits_mode && (rc = rfim_set_spin_storage(h, RFIM_SPINS_BYTES))) return rc;   // shapes are the byte kernels'
     HIPCHK(hipStreamSynchronize(h->stream));
     h->mode = mode;
     h->nw = nw;
@@ -1099,6 +1152,8 @@ int rfim_get_launch_shape(const rfim_t *h, int *mode, int *nw, int *wg) {
 int rfim_set_measure(rfim_t *h, int flags) {
     if (!h) return fail(RFIM_EINVAL, "handle is NULL");
     if (flags & ~RFIM_MEASURE_FOURIER) return fail(RFIM_EINVAL, "unknown measurement flags %d", flags);
+    int rc0;
+    if (flags && h->bits_mode && (rc0 = rfim_set_spin_storage(h, RFIM_SPINS_BYTES))) return rc0;   // it reads bytes
     if ((flags & RFIM_MEASURE_FOURIER) && !h->d_fpart) {
         const size_t L = (size_t)h->L, Rc = (size_t)h->R_cap;
         if (dev_alloc(h, (void **)&h->d_fpart, Rc * L * 2 * L * sizeof(int32_t)) ||
@@ -1159,6 +1214,8 @@ int rfim_set_update_order(rfim_t *h, int order, int tx, int ty, int tz, int hits
     if (order != RFIM_ORDER_CHECKERBOARD && order != RFIM_ORDER_TILES)
         return fail(RFIM_EINVAL, "unknown update order %d", order);
     if (order == RFIM_ORDER_TILES) {
+        int rc0;
+        if (h->bits_mode && (rc0 = rfim_set_spin_storage(h, RFIM_SPINS_BYTES))) return rc0;   // tiles run on bytes
         const rfim_dev::TileShape ts = {tx, ty, tz, hits};
         if (!rfim_dev::tile_shape_valid(h->L, ts))
             return fail(RFIM_EINVAL,
@@ -1175,6 +1232,44 @@ int rfim_set_update_order(rfim_t *h, int order, int tx, int ty, int tz, int hits
     }
     h->order = order;
     return RFIM_OK;
+}
+
+int rfim_set_spin_storage(rfim_t *h, int storage) {
+    if (!h) return fail(RFIM_EINVAL, "handle is NULL");
+    if (h->in_batch) return fail(RFIM_ESTATE, "batch and pool items keep byte spins");
+    if (storage != RFIM_SPINS_BYTES && storage != RFIM_SPINS_BITS)
+        return fail(RFIM_EINVAL, "unknown spin storage %d", storage);
+    if (storage == (h->bits_mode ? RFIM_SPINS_BITS : RFIM_SPINS_BYTES)) return RFIM_OK;
+    if (storage == RFIM_SPINS_BITS) {
+        if (!rfim_dev::bits_valid(h->L))
+            return fail(RFIM_EINVAL, "one bit per spin needs L = 64, 128 or 256 (got %d)", h->L);
+        if (h->order != RFIM_ORDER_CHECKERBOARD)
+            return fail(RFIM_ESTATE, "one bit per spin runs the plain checkerboard order");
+        if (h->measure) return fail(RFIM_ESTATE, "turn the Fourier measurement off first");
+        if (!h->d_bits) {
+            const size_t words = (size_t)h->R_cap * (size_t)h->N / 32;
+            int rc = dev_alloc(h, (void **)&h->d_bits, words * 4);
+            if (!rc && h->kind == 0) rc = dev_alloc(h, (void **)&h->d_fbw, (size_t)h->N / 8);
+            if (rc) {
+                dev_free(h, (void *)h->d_bits);
+                h->d_bits = nullptr;
+                return rc;
+            }
+        }
+        h->bits_mode = true;
+        HIPCHK(rfim_dev::launch_pack_bits(h->lattice(), h->stream));
+        h->nblk = rfim_dev::bits_blocks_per_replica(h->L);
+    } else {
+        HIPCHK(rfim_dev::launch_unpack_bits(h->lattice(), h->stream));
+        h->bits_mode = false;
+        h->nblk = rfim_dev::blocks_per_replica(h->L, h->mode, h->nw, h->wg);
+    }
+    return sync_descriptor(h);
+}
+
+int rfim_get_spin_storage(const rfim_t *h) {
+    if (!h) return fail(RFIM_EINVAL, "handle is NULL");
+    return h->bits_mode ? RFIM_SPINS_BITS : RFIM_SPINS_BYTES;
 }
 
 int rfim_get_update_order(const rfim_t *h, int *order, int *tx, int *ty, int *tz, int *hits) {

@@ -60,6 +60,12 @@ struct Lattice {
     double *E;
     double *Mr;
     double *obs;
+    // one bit per spin (rfim_set_spin_storage): bits uint32 [R_cap][2][N/64],
+    // colour c, word w = sublattice indices 32w..32w+31 (bit q = index
+    // 32w+q), 1 iff s = +1; fbw uint32 [2][N/64], 1 iff h_i = +1 (+-1
+    // fields).  Null while the spins live in `spins`.
+    uint32_t *bits;
+    const uint32_t *fbw;
 };
 
 // Above this many workgroups per replica the streaming sweep does not write
@@ -108,6 +114,18 @@ bool tile_shape_valid(int L, const TileShape &ts);
 size_t tile_lds_bytes(const TileShape &ts);
 // The tiles of coarse colour `coarse` of every replica at sweep t + toff.
 hipError_t launch_tile_sweep(const Lattice &lat, const TileShape &ts, int coarse, int toff, hipStream_t s);
+
+// One bit per spin: L = 2^l with 64 <= L <= 256.  Workgroups per replica
+// of a bit half-sweep (each writes one energy partial with ENERGY).
+bool bits_valid(int L);
+int bits_blocks_per_replica(int L);
+// Half-sweep of colour `colour` at sweep t + toff for replicas r0..r0+nrep-1
+// (energy != 0 on colour 1: also the energy partials of the final state).
+hipError_t launch_bits_sweep(const Lattice &lat, int r0, int nrep, int colour, int toff, int energy, hipStream_t s);
+// Byte spins <-> bit spins of replicas [0, R) (and, to bits, the +-1 field
+// words).
+hipError_t launch_pack_bits(const Lattice &lat, hipStream_t s);
+hipError_t launch_unpack_bits(const Lattice &lat, hipStream_t s);
 
 hipError_t launch_init(const Lattice &lat, int r0, int r1, hipStream_t s);
 // Streaming half-sweep of colour `colour` at sweep t + toff (power-of-two

@@ -369,6 +369,19 @@ __device__ __forceinline__ uint32_t cont_bound(float up, float spin, float hfs, 
     return cvt_u32_sat(p * 0x1p32f);
 }
 
+// Continuous fields: four sites of one Philox block; bit q set iff site q
+// flips.
+__device__ __forceinline__ uint32_t continuous_acc(uint32_t U, uint32_t Wown, const f32x4 hf, float twoJ, float a,
+                                                   const Words &rw) {
+    const float up0 = (float)(U & 0xFFu), up1 = (float)((U >> 8) & 0xFFu);
+    const float up2 = (float)((U >> 16) & 0xFFu), up3 = (float)(U >> 24);
+    const float s0 = (float)(Wown & 0xFFu), s1 = (float)((Wown >> 8) & 0xFFu);
+    const float s2 = (float)((Wown >> 16) & 0xFFu), s3 = (float)(Wown >> 24);
+    const uint32_t b0 = cont_bound(up0, s0, hf.x, twoJ, a), b1 = cont_bound(up1, s1, hf.y, twoJ, a);
+    const uint32_t b2 = cont_bound(up2, s2, hf.z, twoJ, a), b3 = cont_bound(up3, s3, hf.w, twoJ, a);
+    return accept_bits(rw.w0, rw.w1, rw.w2, rw.w3, b0, b1, b2, b3);
+}
+
 // Continuous fields: four sites of one Philox block.
 __device__ __forceinline__ uint32_t continuous_flips(uint32_t U, uint32_t Wown, const f32x4 hf, float twoJ,
                                                      float a, const Words &rw) {
@@ -752,6 +765,180 @@ __global__ __launch_bounds__(1024) void sweep_tiles(Lattice lat, TileShape ts, i
 #pragma unroll
     for (uint32_t c = 0; c < 2; ++c)
         *(GAS uint32_t *)(spins + (size_t)c * half + j0) = *(const uint32_t *)(box + c * plane + mid);
+}
+
+// ---------------------------------------------------------------------
+// One bit per spin (multi-spin coding), L = 2^l in [64, 256].  Colour c of
+// replica r is N/64 words; word w holds sublattice indices 32w..32w+31, a
+// row (y, z) of one colour is L/64 consecutive words.  One thread per word
+// of the updated colour: the other colour's words around it are the pair
+// word W (the same indices), W shifted by one index along the row with the
+// neighbouring word's end bit (pair m-1 when (c+y+z) is even, m+1 when odd,
+// as in the byte layout), and the words of rows y+-1 and z+-1.  A
+// bit-sliced full-adder tree turns the six into three planes of the up
+// count; per Philox block (four indices) the planes' nibbles are spread to
+// bytes and the decision is the byte sweep's, so the chain is the same.
+// ---------------------------------------------------------------------
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+__device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);
+}
+// bits 4b..4b+3 of v to bit 0 of bytes 0..3
+__device__ __forceinline__ uint32_t spread_nibble(uint32_t v, uint32_t b) {
+    return __umul24((v >> (4u * b)) & 0xFu, 0x204081u) & 0x01010101u;
+}
+
+constexpr int kBitsThreads = 256;
+
+__host__ __device__ constexpr int bits_wg(int L) { return L == 64 ? 128 : 256; }
+
+template <int KIND, int ENERGY>
+__global__ __launch_bounds__(kBitsThreads) void sweep_bits(Lattice lat, int colour, int toff, int r0, int lbpr,
+                                                          int remap) {
+    __shared__ uint32_t sthr[32];
+    uint32_t blk = blockIdx.x;
+    if (remap) {
+        const uint32_t per = gridDim.x >> 3;
+        blk = (blk & 7u) * per + (blk >> 3);
+    }
+    const uint32_t r = (uint32_t)r0 + (blk >> lbpr);
+    const uint32_t gb = blk & ((1u << lbpr) - 1u);
+    const uint32_t L = (uint32_t)lat.L, l = (uint32_t)lat.log2L;
+    const uint32_t W1 = (uint32_t)lat.N >> 6;            // words per colour
+    const uint32_t rw_ = L >> 6;                         // words per row
+    const uint32_t w = gb * blockDim.x + threadIdx.x;
+    const uint32_t row = w / rw_, wr = w & (rw_ - 1u);
+    const uint32_t y = row & (L - 1u), z = row >> l;
+    const uint32_t c = (uint32_t)colour;
+    const uint32_t p = (c + y + z) & 1u;
+    GAS uint32_t *own = gptr(lat.bits) + ((size_t)r * 2u + c) * W1;
+    GAS const uint32_t *oth = gptr(lat.bits) + ((size_t)r * 2u + (1u - c)) * W1;
+    const uint32_t base = row * rw_;
+    const uint32_t S = own[w];
+    const uint32_t W = oth[w];
+    const uint32_t Wn = oth[base + ((wr + (p ? 1u : rw_ - 1u)) & (rw_ - 1u))];
+    const uint32_t Wyp = oth[(((y + 1u) & (L - 1u)) + L * z) * rw_ + wr];
+    const uint32_t Wym = oth[(((y - 1u) & (L - 1u)) + L * z) * rw_ + wr];
+    const uint32_t Wzp = oth[(y + L * ((z + 1u) & (L - 1u))) * rw_ + wr];
+    const uint32_t Wzm = oth[(y + L * ((z - 1u) & (L - 1u))) * rw_ + wr];
+    uint32_t F = 0;
+    f32x4 HF[8];
+    if (KIND == 0) {
+        F = gptr(lat.fbw)[(size_t)c * W1 + w];
+    } else {
+        GAS const f32x4 *hf = (GAS const f32x4 *)(gptr(lat.fhf) + (size_t)c * lat.half + 32u * w);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) HF[b] = hf[b];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    const int slot = gptr(lat.r2t)[r];
+    const uint32_t t = (uint32_t)(gptr(lat.ctrs)[0] + (uint64_t)toff);
+    uint32_t never = 0;
+    if (KIND == 0) {
+        if (threadIdx.x < 32u) sthr[threadIdx.x] = gptr(lat.thr)[slot * 32 + threadIdx.x];
+        __syncthreads();
+        never = __builtin_amdgcn_readfirstlane(sthr[31]);
+    }
+    const float beta = KIND == 1 ? gptr(lat.betaf)[slot] : 0.0f;
+    // the x neighbour: index m-1 (p = 0) or m+1 (p = 1) of the row, across
+    // the word boundary (and around the row)
+    const uint32_t Wx = p ? __builtin_amdgcn_alignbit(Wn, W, 1u) : __builtin_amdgcn_alignbit(W, Wn, 31u);
+    // up count of the six neighbours in three bit planes
+    const uint32_t s1 = xor3(W, Wx, Wyp), c1 = maj3(W, Wx, Wyp);
+    const uint32_t s2 = xor3(Wym, Wzp, Wzm), c2 = maj3(Wym, Wzp, Wzm);
+    const uint32_t U0 = s1 ^ s2, c3 = s1 & s2;
+    const uint32_t U1 = xor3(c1, c2, c3), U2 = maj3(c1, c2, c3);
+    const uint32_t c1w = 2u * t + c, c3w = (kTagSweep << 28) | lat.rho;
+    const uint8_t *tb = (const uint8_t *)sthr;
+    uint32_t flips = 0;
+#pragma unroll
+    for (uint32_t b = 0; b < 8; ++b) {
+        const Words rw = philox10(8u * w + b, c1w, r, c3w, lat.key0, lat.key1);
+        const uint32_t Ub = spread_nibble(U0, b) | (spread_nibble(U1, b) << 1) | (spread_nibble(U2, b) << 2);
+        const uint32_t Sb = spread_nibble(S, b);
+        uint32_t acc;
+        if (KIND == 0) {
+            const uint32_t A = (Ub << 4) | (Sb << 3) | (spread_nibble(F, b) << 2);
+            const uint32_t a0 = A & 0xFFu, a1 = (A >> 8) & 0xFFu, a2 = (A >> 16) & 0xFFu, a3 = A >> 24;
+            const uint32_t th0 = *(const uint32_t *)(tb + a0), th1 = *(const uint32_t *)(tb + a1);
+            const uint32_t th2 = *(const uint32_t *)(tb + a2), th3 = *(const uint32_t *)(tb + a3);
+            acc = accept_bits(rw.w0, rw.w1, rw.w2, rw.w3, th0, th1, th2, th3);
+            if (never != 0u) {
+                // a class that can never flip at this temperature has entry
+                // 0, which u = 0 would meet
+                const uint32_t umin = min(min(rw.w0, rw.w1), min(rw.w2, rw.w3));
+                if (umin == 0u) {
+                    if (rw.w0 == 0u && ((never >> (a0 >> 2)) & 1u)) acc &= ~1u;
+                    if (rw.w1 == 0u && ((never >> (a1 >> 2)) & 1u)) acc &= ~2u;
+                    if (rw.w2 == 0u && ((never >> (a2 >> 2)) & 1u)) acc &= ~4u;
+                    if (rw.w3 == 0u && ((never >> (a3 >> 2)) & 1u)) acc &= ~8u;
+                }
+            }
+        } else {
+            acc = continuous_acc(Ub, Sb, HF[b], 2.0f * lat.Jf, -2.0f * 1.44269504088896341f * beta, rw);
+        }
+        flips |= acc << (4u * b);
+    }
+    const uint32_t Snew = S ^ flips;
+    if (flips) own[w] = Snew;
+    if (ENERGY) {
+        // colour 1 of the last sweep before an exchange: the final state.
+        // B counts each bond once through the colour-1 sites: sum of
+        // s_i n_i = 2 K - 6 with K the aligned neighbours (up if s = +1,
+        // 6 - up if s = -1).
+        const uint32_t nS = ~Snew;
+        const int up_on = __popc(U0 & Snew) + 2 * __popc(U1 & Snew) + 4 * __popc(U2 & Snew);
+        const int up_off = __popc(U0 & nS) + 2 * __popc(U1 & nS) + 4 * __popc(U2 & nS);
+        const int ksum = up_on + 6 * (32 - __popc(Snew)) - up_off;
+        const int upsum = __popc(Snew) + __popc(W);
+        int eqsum = 0;
+        double fsum = 0.0;
+        if (KIND == 0) {
+            const uint32_t F0 = gptr(lat.fbw)[w];
+            eqsum = __popc(~(Snew ^ F)) + __popc(~(W ^ F0));
+        } else {
+            GAS const float *f1 = gptr(lat.fraw) + lat.half + 32u * w;
+            GAS const float *f0 = gptr(lat.fraw) + 32u * w;
+#pragma unroll 8
+            for (uint32_t q = 0; q < 32; ++q) {
+                fsum += ((Snew >> q) & 1u) ? (double)f1[q] : -(double)f1[q];
+                fsum += ((W >> q) & 1u) ? (double)f0[q] : -(double)f0[q];
+            }
+        }
+        block_partial<KIND>(gptr(lat.part) + ((size_t)gb * lat.pstride + r) * 3, 32, ksum, upsum, eqsum, fsum);
+    }
+}
+
+// Byte spins <-> bit spins (one thread per 32-site word) and the +-1 field
+// words.
+__global__ __launch_bounds__(256) void pack_bits_kernel(Lattice lat) {
+    const uint32_t W1 = (uint32_t)lat.N >> 6;
+    const uint32_t e = blockIdx.x * 256u + threadIdx.x;     // word of (replica, colour)
+    if (e >= (uint32_t)lat.R * 2u * W1) return;
+    const uint8_t *src = lat.spins + (size_t)e * 32u;       // [r][c][32w..] matches the byte layout
+    uint32_t v = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < 32; ++q) v |= (uint32_t)(src[q] & 1u) << q;
+    lat.bits[e] = v;
+    if (e < 2u * W1 && lat.kind == 0) {
+        uint32_t f = 0;
+        const uint8_t *fb = lat.fbits + (size_t)e * 32u;
+#pragma unroll
+        for (uint32_t q = 0; q < 32; ++q) f |= (uint32_t)((fb[q] >> 2) & 1u) << q;
+        ((uint32_t *)lat.fbw)[e] = f;
+    }
+}
+
+__global__ __launch_bounds__(256) void unpack_bits_kernel(Lattice lat) {
+    const uint32_t W1 = (uint32_t)lat.N >> 6;
+    const uint32_t e = blockIdx.x * 256u + threadIdx.x;
+    if (e >= (uint32_t)lat.R * 2u * W1) return;
+    const uint32_t v = lat.bits[e];
+    uint8_t *dst = lat.spins + (size_t)e * 32u;
+#pragma unroll
+    for (uint32_t q = 0; q < 32; ++q) dst[q] = (uint8_t)((v >> q) & 1u);
 }
 
 // ---------------------------------------------------------------------
@@ -1168,6 +1355,40 @@ hipError_t launch_tile_sweep(const Lattice &lat, const TileShape &ts, int coarse
         hipLaunchKernelGGL(sweep_tiles<0>, grid, block, tile_lds_bytes(ts), s, lat, ts, coarse, toff);
     else
         hipLaunchKernelGGL(sweep_tiles<1>, grid, block, tile_lds_bytes(ts), s, lat, ts, coarse, toff);
+    return hipGetLastError();
+}
+
+bool bits_valid(int L) { return L == 64 || L == 128 || L == 256; }
+
+int bits_blocks_per_replica(int L) { return (int)(((long long)L * L * L / 64) / bits_wg(L)); }
+
+hipError_t launch_bits_sweep(const Lattice &lat, int r0, int nrep, int colour, int toff, int energy, hipStream_t s) {
+    if (nrep <= 0) return hipSuccess;
+    const int bpr = bits_blocks_per_replica(lat.L);
+    const int lbpr = __builtin_ctz((unsigned)bpr);
+    const int nb = bpr * nrep;
+    const int remap = nb % 8 == 0 ? 1 : 0;
+    const dim3 grid((unsigned)nb), block((unsigned)bits_wg(lat.L));
+    const bool e = energy && colour == 1;
+    if (lat.kind == 0) {
+        if (e) hipLaunchKernelGGL((sweep_bits<0, 1>), grid, block, 0, s, lat, colour, toff, r0, lbpr, remap);
+        else hipLaunchKernelGGL((sweep_bits<0, 0>), grid, block, 0, s, lat, colour, toff, r0, lbpr, remap);
+    } else {
+        if (e) hipLaunchKernelGGL((sweep_bits<1, 1>), grid, block, 0, s, lat, colour, toff, r0, lbpr, remap);
+        else hipLaunchKernelGGL((sweep_bits<1, 0>), grid, block, 0, s, lat, colour, toff, r0, lbpr, remap);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_bits(const Lattice &lat, hipStream_t s) {
+    const long long words = (long long)lat.R * 2 * (lat.N / 64);
+    hipLaunchKernelGGL(pack_bits_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, lat);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_bits(const Lattice &lat, hipStream_t s) {
+    const long long words = (long long)lat.R * 2 * (lat.N / 64);
+    hipLaunchKernelGGL(unpack_bits_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, lat);
     return hipGetLastError();
 }
 

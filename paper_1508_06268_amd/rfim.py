@@ -37,8 +37,10 @@ EXPORTS = [
     "rfim_pool_adapt", "rfim_pool_release", "rfim_pool_item",
     "rfim_pool_active", "rfim_pool_reserved", "rfim_pool_set_shape", "rfim_pool_synchronize",
     "rfim_energies_noalloc", "rfim_set_update_order", "rfim_get_update_order",
+    "rfim_set_spin_storage", "rfim_get_spin_storage",
 ]
 ORDER_CHECKERBOARD, ORDER_TILES = 0, 1
+SPINS_BYTES, SPINS_BITS = 0, 1
 NOALLOC_MAX_PARTIALS = 1 << 18
 
 
@@ -122,6 +124,8 @@ def load_library(path: str = LIB_PATH):
         "rfim_energies_noalloc": (i32, [i32, i32, dbl, dbl, vp, vp, vp, vp]),
         "rfim_set_update_order": (i32, [vp, i32, i32, i32, i32, i32]),
         "rfim_get_update_order": (i32, [vp, vp, vp, vp, vp, vp]),
+        "rfim_set_spin_storage": (i32, [vp, i32]),
+        "rfim_get_spin_storage": (i32, [vp]),
         "rfim_adapt_temps": (i32, [vp, i32, i64, i32, dbl, i32, i32]),
         "rfim_destroy": (None, [vp]),
         "rfim_last_error": (C.c_char_p, []),
@@ -423,6 +427,13 @@ class Rfim:
         `hits` local sweeps per tile visit (see rfim_set_update_order)."""
         tx, ty, tz = (int(v) for v in tiles)
         _check(load_library().rfim_set_update_order(self._h, int(order), tx, ty, tz, int(hits)))
+
+    def set_spin_storage(self, storage: int):
+        """SPINS_BYTES or SPINS_BITS (one bit per spin, L = 64/128/256)."""
+        _check(load_library().rfim_set_spin_storage(self._h, int(storage)))
+
+    def spin_storage(self) -> int:
+        return _check(load_library().rfim_get_spin_storage(self._h))
 
     def update_order(self):
         """(order, (tx, ty, tz), hits)."""
