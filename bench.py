@@ -41,6 +41,11 @@ VALU_FILE = os.path.join(ROOT, "profiles", "sweep_pow2_l64_r192_valu.txt")
 # shared by every replica of a realization, so a launch over R replicas
 # needs it once: 3 + f/R bytes per attempt is the floor with perfect reuse.
 BYTES_PER_ATTEMPT = {0: 4.0, 1: 7.0}
+# One bit per spin: the site, the other colour and the +-1 field are 1/8
+# byte each, and the site is written: 0.5 B per attempt.
+BITS_BYTES_PER_ATTEMPT = 0.5
+TRAFFIC_BITS_FILE = os.path.join(ROOT, "profiles", "sweep_bits_l64_r192_traffic.txt")
+VALU_BITS_FILE = os.path.join(ROOT, "profiles", "sweep_bits_l64_r192_valu.txt")
 FIELD_BYTES = {0: 1.0, 1: 4.0}
 # Vector ALU issue: 256 CUs x 4 SIMDs, a wave64 instruction occupies its SIMD
 # for 4 cycles at full rate, so 256 x 4 x 2.4e9 / 4 = 0.614e12 wave-instruction
@@ -72,14 +77,14 @@ def _profile_value(path, pattern):
     return float(m_val.group(1))
 
 
-def measured_traffic():
-    """HBM bytes per launch of the sweep kernel (FETCH_SIZE + WRITE_SIZE)."""
-    return _profile_value(TRAFFIC_FILE, r"hbm_bytes_per_launch:\s*([0-9.eE+]+)")
+def measured_traffic(path):
+    """HBM bytes per launch of a sweep kernel (FETCH_SIZE + WRITE_SIZE)."""
+    return _profile_value(path, r"hbm_bytes_per_launch:\s*([0-9.eE+]+)")
 
 
-def measured_valu_per_wave():
-    """VALU instructions per wave of the sweep kernel (SQ_INSTS_VALU / SQ_WAVES)."""
-    return _profile_value(VALU_FILE, r"VALU instructions per wave:\s*([0-9.]+)")
+def measured_valu_per_1024(path):
+    """VALU wave-instructions per 1024 attempts of a sweep kernel."""
+    return _profile_value(path, r"VALU instructions per 1024 attempts:\s*([0-9.]+)")
 
 
 def run_realization(h, w, stream, torch):
@@ -141,17 +146,53 @@ def cpu_baseline(w, lib_path, sweeps=20):
                       "gcc -O3 -march=native -ffp-contract=off)" % (w.L, w.R, sweeps, w.every, att, dt)}
 
 
-def kernel_only(torch, P, W, sweeps):
-    """Only the dominant kernel at the production shape (L=64, R=192, +-1
-    fields): `sweeps` sweeps without exchange, for counter collection."""
+def kernel_only(torch, P, W, sweeps, storage):
+    """Only a sweep kernel at the production shape (L=64, R=192, +-1
+    fields; byte or bit storage): `sweeps` sweeps without exchange on one
+    stream, for counter collection."""
     w = W.adaptive_l64()
     stream = torch.cuda.Stream()
     h = P.Rfim(w.L, w.R_cap, w.J, w.h, w.fields, W.linear_temps(w.R_cap, 1.0, 6.0), seed=w.seed,
                stream=stream)
+    h.set_spin_storage(storage)
     h.set_concurrency(1)
     h.sweep(sweeps, 0)
     h.synchronize()
-    log("kernel mode: %d half-sweep launches at L=%d R=%d" % (2 * sweeps, w.L, w.R_cap))
+    log("kernel mode: %d half-sweep launches at L=%d R=%d, %s" % (2 * sweeps, w.L, w.R_cap,
+                                                                 "bits" if storage else "bytes"))
+
+
+def hbm_bits_leg(torch, P, W, n=128, R=128, sweeps=100, every=10):
+    """One bit per spin on data of the HBM-streaming leg's byte size: n
+    realizations x R=128 at L=64 (512 MiB of spin bits at n = 128), each a
+    handle in bit storage, swept one after another on one stream."""
+    stream = torch.cuda.Stream()
+    hs = []
+    for q in range(n):
+        g = P.Rfim(64, R, 1.0, 2.25, W.bimodal_fields(64, [9, q]), W.linear_temps(R, 1.0, 6.0), seed=0,
+                   realization=q, stream=stream)
+        assert g.spin_storage() == P.rfim.SPINS_BITS
+        g.sweep(every, every)
+        hs.append(g)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for g in hs:
+        g.sweep(sweeps, every)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    dt = e0.elapsed_time(e1) / 1e3
+    for g in hs:
+        g.close()
+    attempts = n * R * 64 ** 3 * sweeps
+    rate = attempts / dt / 1e9
+    mib = n * R * 64 ** 3 / 8 / 2 ** 20
+    log("hbm-size bits: %d x L=64 R=%d (%.0f MiB of spin bits), %d sweeps each: %.1f attempts/ns"
+        % (n, R, mib, sweeps, rate))
+    return {"workload": "hbm_size_bits_l64", "realizations": n, "L": 64, "R": R, "spin_bits_mib": round(mib, 1),
+            "sweeps": sweeps, "exchange_every": every, "attempts_per_ns": round(rate, 1),
+            "hbm_gbs_algorithmic": round(rate * BITS_BYTES_PER_ATTEMPT, 1)}
 
 
 def tiles_only(torch, P, W, sweeps=2, hits=100, tiles=(32, 8, 8)):
@@ -485,8 +526,9 @@ def main():
                     help="served_stream: only the continuous-batching serving run (its own JSON line)")
     ap.add_argument("--production-sweeps", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="bench", choices=["bench", "kernel", "tiles", "streaming", "copy"],
-                    help="kernel: only the dominant kernel (for counters); tiles: only the multi-hit "
+    ap.add_argument("--mode", default="bench", choices=["bench", "kernel", "kernel_bits", "tiles", "streaming", "copy"],
+                    help="kernel / kernel_bits: only the byte / bit sweep kernel (for counters); tiles: only "
+                         "the multi-hit "
                          "tile kernel (for counters); streaming: only the "
                          "HBM-streaming leg; copy: a plain copy of --copy-bytes (counter calibration)")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
@@ -494,6 +536,8 @@ def main():
     ap.add_argument("--no-served", action="store_true", help="skip the served-stream leg")
     ap.add_argument("--trace-summary", default=None, metavar="KERNEL_TRACE_CSV",
                     help="print per (kernel, grid) statistics of a rocprofv3 kernel trace and exit")
+    ap.add_argument("--kernel-match", default="sweep_pow2",
+                    help="with --traffic-summary: the kernel name to match (sweep_pow2, sweep_bits)")
     ap.add_argument("--traffic-summary", nargs=4, default=None,
                     metavar=("FETCH_KERNEL_CSV", "FETCH_COPY_CSV", "WRITE_KERNEL_CSV", "WRITE_COPY_CSV"),
                     help="print the calibrated FETCH_SIZE + WRITE_SIZE bytes per sweep launch and exit")
@@ -508,7 +552,8 @@ def main():
         return
     if args.traffic_summary:
         fk, fc, wk, wc = args.traffic_summary
-        a, b = counter_summary(fk, fc, "FETCH_SIZE"), counter_summary(wk, wc, "WRITE_SIZE")
+        a = counter_summary(fk, fc, "FETCH_SIZE", args.kernel_match)
+        b = counter_summary(wk, wc, "WRITE_SIZE", args.kernel_match)
         for d in (a, b):
             print("%s: %d dispatches, mean %.1f KiB (min %.1f, max %.1f); copy calibration %.1f KiB per 1 GiB "
                   "-> factor %.4f -> %.4e bytes" % (d["counter"], d["dispatches"], d["mean_kib"], d["min_kib"],
@@ -525,8 +570,8 @@ def main():
     from paper_1508_06268_amd import workloads as W
 
     torch.cuda.set_device(0)
-    if args.mode == "kernel":
-        kernel_only(torch, P, W, 20)
+    if args.mode in ("kernel", "kernel_bits"):
+        kernel_only(torch, P, W, 20, P.rfim.SPINS_BITS if args.mode == "kernel_bits" else P.rfim.SPINS_BYTES)
         return
     if args.mode == "tiles":
         tiles_only(torch, P, W)
@@ -584,13 +629,13 @@ def main():
         % (args.steps, attempts, wall, gpu_ms / 1e3, value))
     log("step ms: %s" % " ".join("%.1f" % t for t in step_ms))
 
-    # Roofline leg: the dominant kernel (one half-sweep of every replica) at
-    # the production shape, timed with events on the handle's stream.
-    # One launch covers every replica (one stream): median of 10 repetitions
-    # of 40 sweeps (80 launches) each.  The production path splits large
-    # half-sweeps over two streams, timed here as well in its steady state:
-    # median of 10 repetitions of 200 sweeps, so that the fork and join of
-    # each call weigh little.
+    # Roofline legs, timed with events on the handle's stream: one launch
+    # over every replica (one stream), median of 10 repetitions of 40
+    # sweeps (80 launches); and the production path's two-stream half-sweep
+    # in its steady state, median of 10 repetitions of 200 sweeps.  The
+    # workload's handles keep one bit per spin (the default for +-1 fields
+    # at L = 64), so its dominant kernel is the bit sweep; the byte sweep is
+    # measured on the same handle beside it.
     h = handles[-1]
     reps = 10
 
@@ -609,48 +654,76 @@ def main():
             times.append(e0.elapsed_time(e1) * 1e3 / (2 * n_roof))
         return float(np.median(times))
 
+    kind = h.field_kind
+    attempts_per_launch = R_final * w.L ** 3 // 2
+    waves_per_launch = attempts_per_launch / 1024.0
+
+    def alu_of(valu_per_1024, us):
+        rate = valu_per_1024 * waves_per_launch / (us * 1e-6)
+        return rate, rate / WAVE_SLOTS_PER_S
+
+    storage = h.spin_storage()
+    bits_legs = None
+    if storage == P.rfim.SPINS_BITS:
+        bits_us = half_sweep_us(1, 40)
+        bits_split_us = half_sweep_us(2, 200)
+        valu_bits = measured_valu_per_1024(VALU_BITS_FILE)
+        b_bytes = BITS_BYTES_PER_ATTEMPT * attempts_per_launch
+        b_gbs = b_bytes / (bits_us * 1e-6) / 1e9
+        bits_legs = {"launch_us": bits_us, "split_us": bits_split_us, "valu": valu_bits, "bytes": b_bytes,
+                     "gbs": b_gbs}
+        log("bit sweep: %.2f us per half-sweep launch (%.1f attempts/ns); two streams: %.2f us"
+            % (bits_us, attempts_per_launch / (bits_us * 1e3), bits_split_us))
+    h.set_spin_storage(P.rfim.SPINS_BYTES)
     launch_us = half_sweep_us(1, 40)
     split_us = half_sweep_us(2, 200)
     h.set_concurrency(0)
     mode, nw, wg = h.launch_shape()
-    kind = h.field_kind
-    attempts_per_launch = R_final * w.L ** 3 // 2
     bytes_per_launch = BYTES_PER_ATTEMPT[kind] * attempts_per_launch
     hbm_gbs = bytes_per_launch / (launch_us * 1e-6) / 1e9
-    traffic = measured_traffic()
-    # VALU: the kernel's measured instructions per wave (1024 attempts per
-    # wave) against the issue rate of the chip, when the counter summary
-    # matches the current kernel source
-    valu_per_wave = measured_valu_per_wave()
-    waves_per_launch = attempts_per_launch / 1024.0
-    alu = None
-    if valu_per_wave:
-        inst_rate = valu_per_wave * waves_per_launch / (launch_us * 1e-6)
-        alu = {"achieved": round(inst_rate / 1e12, 4), "peak": round(WAVE_SLOTS_PER_S / 1e12, 4),
-               "unit": "T wave-instructions/s", "frac": round(inst_rate / WAVE_SLOTS_PER_S, 4),
-               "valu_per_wave": valu_per_wave,
-               "two_streams_frac": round(valu_per_wave * waves_per_launch / (split_us * 1e-6)
-                                         / WAVE_SLOTS_PER_S, 4)}
-    roofline = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(hbm_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "sweep_pow2<bimodal, %d dwords x %d threads>, one launch over R=%d" % (nw, wg, R_final),
-                "launch_us": round(launch_us, 3), "attempts_per_launch": attempts_per_launch,
-                "bytes_per_attempt": BYTES_PER_ATTEMPT[kind], "bytes_per_launch": bytes_per_launch,
-                "attempts_per_ns_kernel": round(attempts_per_launch / (launch_us * 1e3), 1),
-                "alu": alu,
-                "two_streams": {"half_sweep_us": round(split_us, 3),
-                                "attempts_per_ns": round(attempts_per_launch / (split_us * 1e3), 1),
-                                "hbm_frac": round(bytes_per_launch / (split_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}}
-    log("roofline: %.2f us per half-sweep launch, %.0f GB/s algorithmic (%.1f%% of HBM); "
+    valu_bytes = measured_valu_per_1024(VALU_FILE)
+    byte_kernel = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "frac": round(hbm_gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(TRAFFIC_FILE),
+                   "kernel": "sweep_pow2<bimodal, %d dwords x %d threads>, one launch over R=%d" % (nw, wg, R_final),
+                   "launch_us": round(launch_us, 3), "attempts_per_launch": attempts_per_launch,
+                   "bytes_per_attempt": BYTES_PER_ATTEMPT[kind], "bytes_per_launch": bytes_per_launch,
+                   "attempts_per_ns_kernel": round(attempts_per_launch / (launch_us * 1e3), 1),
+                   "valu_frac": round(alu_of(valu_bytes, launch_us)[1], 4) if valu_bytes else None,
+                   "two_streams": {"half_sweep_us": round(split_us, 3),
+                                   "attempts_per_ns": round(attempts_per_launch / (split_us * 1e3), 1),
+                                   "hbm_frac": round(bytes_per_launch / (split_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}}
+    log("byte sweep: %.2f us per half-sweep launch, %.0f GB/s algorithmic (%.1f%% of HBM); "
         "two streams: %.2f us per half-sweep" % (launch_us, hbm_gbs, 100 * hbm_gbs / HBM_PEAK_GBS, split_us))
-    if alu:
-        log("VALU: %.1f%% of issue slots (one launch), %.1f%% (two streams)"
-            % (100 * alu["frac"], 100 * alu["two_streams_frac"]))
+    if bits_legs and bits_legs["valu"]:
+        rate, frac = alu_of(bits_legs["valu"], bits_legs["launch_us"])
+        roofline = {"bound": "alu", "achieved": round(rate / 1e12, 4), "peak": round(WAVE_SLOTS_PER_S / 1e12, 4),
+                    "unit": "T wave-instructions/s", "frac": round(frac, 4),
+                    "traffic": measured_traffic(TRAFFIC_BITS_FILE),
+                    "kernel": "sweep_bits<bimodal>, one launch over R=%d" % R_final,
+                    "launch_us": round(bits_legs["launch_us"], 3), "attempts_per_launch": attempts_per_launch,
+                    "valu_per_1024_attempts": bits_legs["valu"],
+                    "attempts_per_ns_kernel": round(attempts_per_launch / (bits_legs["launch_us"] * 1e3), 1),
+                    "hbm": {"achieved": round(bits_legs["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": round(bits_legs["gbs"] / HBM_PEAK_GBS, 4),
+                            "bytes_per_attempt": BITS_BYTES_PER_ATTEMPT, "bytes_per_launch": bits_legs["bytes"]},
+                    "two_streams": {"half_sweep_us": round(bits_legs["split_us"], 3),
+                                    "attempts_per_ns": round(attempts_per_launch / (bits_legs["split_us"] * 1e3), 1),
+                                    "alu_frac": round(alu_of(bits_legs["valu"], bits_legs["split_us"])[1], 4)},
+                    "byte_kernel": byte_kernel}
+        log("VALU of the bit sweep: %.1f%% of issue (one launch), %.1f%% (two streams)"
+            % (100 * frac, 100 * roofline["two_streams"]["alu_frac"]))
+    else:
+        roofline = dict(byte_kernel)
+        if bits_legs:
+            roofline["bit_kernel"] = {"launch_us": round(bits_legs["launch_us"], 3),
+                                      "two_streams_half_sweep_us": round(bits_legs["split_us"], 3),
+                                      "hbm_gbs_algorithmic": round(bits_legs["gbs"], 1)}
 
     for hh in handles:
         hh.close()
     streaming = hbm_streaming_leg(torch, P, W)
     roofline["hbm_streaming"] = streaming
+    roofline["hbm_size_bits"] = hbm_bits_leg(torch, P, W)
     paper_scale = paper_scale_leg(torch, P, W)
     batched = None if args.no_batched else batched_leg(torch, P, W)
     served = None if args.no_served else served_leg(torch, P, W)

@@ -61,9 +61,9 @@ struct Lattice {
     double *Mr;
     double *obs;
     // one bit per spin (rfim_set_spin_storage): bits uint32 [R_cap][2][N/64],
-    // colour c, word w = sublattice indices 32w..32w+31 (bit q = index
-    // 32w+q), 1 iff s = +1; fbw uint32 [2][N/64], 1 iff h_i = +1 (+-1
-    // fields).  Null while the spins live in `spins`.
+    // colour c, word w = sublattice indices 32w..32w+31 (index 32w+4b+q at
+    // bit 8q+b), 1 iff s = +1; fbw uint32 [2][N/64] in the same order,
+    // 1 iff h_i = +1 (+-1 fields).  Null while the spins live in `spins`.
     uint32_t *bits;
     const uint32_t *fbw;
 };

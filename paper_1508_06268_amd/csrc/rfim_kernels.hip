@@ -769,15 +769,17 @@ __global__ __launch_bounds__(1024) void sweep_tiles(Lattice lat, TileShape ts, i
 
 // ---------------------------------------------------------------------
 // One bit per spin (multi-spin coding), L = 2^l in [64, 256].  Colour c of
-// replica r is N/64 words; word w holds sublattice indices 32w..32w+31, a
-// row (y, z) of one colour is L/64 consecutive words.  One thread per word
-// of the updated colour: the other colour's words around it are the pair
-// word W (the same indices), W shifted by one index along the row with the
-// neighbouring word's end bit (pair m-1 when (c+y+z) is even, m+1 when odd,
-// as in the byte layout), and the words of rows y+-1 and z+-1.  A
-// bit-sliced full-adder tree turns the six into three planes of the up
-// count; per Philox block (four indices) the planes' nibbles are spread to
-// bytes and the decision is the byte sweep's, so the chain is the same.
+// replica r is N/64 words; word w holds sublattice indices 32w..32w+31,
+// index 32w + 4b + q at bit 8q + b, so that the four sites of Philox block
+// 8w + b sit at bit b of the four bytes.  A row (y, z) of one colour is
+// L/64 consecutive words.  One thread per word of the updated colour: the
+// other colour's words around it are the pair word W (the same indices), W
+// shifted by one index along the row with the neighbouring word's end bit
+// (index m-1 when (c+y+z) is even, m+1 when odd, as in the byte layout),
+// and the words of rows y+-1 and z+-1.  A bit-sliced full-adder tree turns
+// the six into three planes of the up count; per Philox block a shift and
+// a mask per plane give the byte-per-site operands of the byte sweep's
+// decision, which runs on the same random words, so the chain is the same.
 // ---------------------------------------------------------------------
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
@@ -785,10 +787,19 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
 __device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);
 }
-// bits 4b..4b+3 of v to bit 0 of bytes 0..3
-__device__ __forceinline__ uint32_t spread_nibble(uint32_t v, uint32_t b) {
-    return __umul24((v >> (4u * b)) & 0xFu, 0x204081u) & 0x01010101u;
+constexpr uint32_t kByteLsb = 0x01010101u;
+// bit b of each byte of v, to bit 0
+__device__ __forceinline__ uint32_t block_bits(uint32_t v, uint32_t b) { return (v >> b) & kByteLsb; }
+// bits 0..3 of a to bit 0 of bytes 0..3: a 24-bit multiply written out, so
+// that a later shift is not folded into a constant the 24-bit form cannot
+// take
+__device__ __forceinline__ uint32_t nibble_to_bytes(uint32_t a) {
+    uint32_t r;
+    asm("v_mul_u32_u24 %0, %1, %2" : "=v"(r) : "s"(0x204081u), "v"(a));
+    return r & kByteLsb;
 }
+// position of sublattice index i (0..31) within its word
+__host__ __device__ constexpr uint32_t bit_of_index(uint32_t i) { return 8u * (i & 3u) + (i >> 2); }
 
 constexpr int kBitsThreads = 256;
 
@@ -807,22 +818,22 @@ __global__ __launch_bounds__(kBitsThreads) void sweep_bits(Lattice lat, int colo
     const uint32_t gb = blk & ((1u << lbpr) - 1u);
     const uint32_t L = (uint32_t)lat.L, l = (uint32_t)lat.log2L;
     const uint32_t W1 = (uint32_t)lat.N >> 6;            // words per colour
-    const uint32_t rw_ = L >> 6;                         // words per row
+    const uint32_t lrw = l - 6u, rw_ = 1u << lrw;        // words per row
     const uint32_t w = gb * blockDim.x + threadIdx.x;
-    const uint32_t row = w / rw_, wr = w & (rw_ - 1u);
+    const uint32_t row = w >> lrw, wr = w & (rw_ - 1u);
     const uint32_t y = row & (L - 1u), z = row >> l;
     const uint32_t c = (uint32_t)colour;
     const uint32_t p = (c + y + z) & 1u;
     GAS uint32_t *own = gptr(lat.bits) + ((size_t)r * 2u + c) * W1;
     GAS const uint32_t *oth = gptr(lat.bits) + ((size_t)r * 2u + (1u - c)) * W1;
-    const uint32_t base = row * rw_;
+    const uint32_t base = row << lrw;
     const uint32_t S = own[w];
     const uint32_t W = oth[w];
     const uint32_t Wn = oth[base + ((wr + (p ? 1u : rw_ - 1u)) & (rw_ - 1u))];
-    const uint32_t Wyp = oth[(((y + 1u) & (L - 1u)) + L * z) * rw_ + wr];
-    const uint32_t Wym = oth[(((y - 1u) & (L - 1u)) + L * z) * rw_ + wr];
-    const uint32_t Wzp = oth[(y + L * ((z + 1u) & (L - 1u))) * rw_ + wr];
-    const uint32_t Wzm = oth[(y + L * ((z - 1u) & (L - 1u))) * rw_ + wr];
+    const uint32_t Wyp = oth[((((y + 1u) & (L - 1u)) + (z << l)) << lrw) + wr];
+    const uint32_t Wym = oth[((((y - 1u) & (L - 1u)) + (z << l)) << lrw) + wr];
+    const uint32_t Wzp = oth[((y + (((z + 1u) & (L - 1u)) << l)) << lrw) + wr];
+    const uint32_t Wzm = oth[((y + (((z - 1u) & (L - 1u)) << l)) << lrw) + wr];
     uint32_t F = 0;
     f32x4 HF[8];
     if (KIND == 0) {
@@ -842,9 +853,12 @@ __global__ __launch_bounds__(kBitsThreads) void sweep_bits(Lattice lat, int colo
         never = __builtin_amdgcn_readfirstlane(sthr[31]);
     }
     const float beta = KIND == 1 ? gptr(lat.betaf)[slot] : 0.0f;
-    // the x neighbour: index m-1 (p = 0) or m+1 (p = 1) of the row, across
-    // the word boundary (and around the row)
-    const uint32_t Wx = p ? __builtin_amdgcn_alignbit(Wn, W, 1u) : __builtin_amdgcn_alignbit(W, Wn, 31u);
+    // the x neighbour, index m-1 (p = 0) or m+1 (p = 1), in the interleaved
+    // order: a step of one index is a step of one byte, with the carry
+    // between byte 3 and byte 0 one bit along, and the end bit from the
+    // neighbouring word of the row (around the row)
+    const uint32_t Wx = p ? ((W >> 8) | ((W << 23) & 0x7F000000u) | (Wn << 31))
+                          : ((W << 8) | ((W >> 23) & 0x000000FEu) | (Wn >> 31));
     // up count of the six neighbours in three bit planes
     const uint32_t s1 = xor3(W, Wx, Wyp), c1 = maj3(W, Wx, Wyp);
     const uint32_t s2 = xor3(Wym, Wzp, Wzm), c2 = maj3(Wym, Wzp, Wzm);
@@ -856,11 +870,11 @@ __global__ __launch_bounds__(kBitsThreads) void sweep_bits(Lattice lat, int colo
 #pragma unroll
     for (uint32_t b = 0; b < 8; ++b) {
         const Words rw = philox10(8u * w + b, c1w, r, c3w, lat.key0, lat.key1);
-        const uint32_t Ub = spread_nibble(U0, b) | (spread_nibble(U1, b) << 1) | (spread_nibble(U2, b) << 2);
-        const uint32_t Sb = spread_nibble(S, b);
+        const uint32_t Ub = block_bits(U0, b) | (block_bits(U1, b) << 1) | (block_bits(U2, b) << 2);
+        const uint32_t Sb = block_bits(S, b);
         uint32_t acc;
         if (KIND == 0) {
-            const uint32_t A = (Ub << 4) | (Sb << 3) | (spread_nibble(F, b) << 2);
+            const uint32_t A = (Ub << 4) | (Sb << 3) | (block_bits(F, b) << 2);
             const uint32_t a0 = A & 0xFFu, a1 = (A >> 8) & 0xFFu, a2 = (A >> 16) & 0xFFu, a3 = A >> 24;
             const uint32_t th0 = *(const uint32_t *)(tb + a0), th1 = *(const uint32_t *)(tb + a1);
             const uint32_t th2 = *(const uint32_t *)(tb + a2), th3 = *(const uint32_t *)(tb + a3);
@@ -879,7 +893,7 @@ __global__ __launch_bounds__(kBitsThreads) void sweep_bits(Lattice lat, int colo
         } else {
             acc = continuous_acc(Ub, Sb, HF[b], 2.0f * lat.Jf, -2.0f * 1.44269504088896341f * beta, rw);
         }
-        flips |= acc << (4u * b);
+        flips |= nibble_to_bytes(acc) << b;
     }
     const uint32_t Snew = S ^ flips;
     if (flips) own[w] = Snew;
@@ -902,9 +916,10 @@ __global__ __launch_bounds__(kBitsThreads) void sweep_bits(Lattice lat, int colo
             GAS const float *f1 = gptr(lat.fraw) + lat.half + 32u * w;
             GAS const float *f0 = gptr(lat.fraw) + 32u * w;
 #pragma unroll 8
-            for (uint32_t q = 0; q < 32; ++q) {
-                fsum += ((Snew >> q) & 1u) ? (double)f1[q] : -(double)f1[q];
-                fsum += ((W >> q) & 1u) ? (double)f0[q] : -(double)f0[q];
+            for (uint32_t i = 0; i < 32; ++i) {
+                const uint32_t q = bit_of_index(i);
+                fsum += ((Snew >> q) & 1u) ? (double)f1[i] : -(double)f1[i];
+                fsum += ((W >> q) & 1u) ? (double)f0[i] : -(double)f0[i];
             }
         }
         block_partial<KIND>(gptr(lat.part) + ((size_t)gb * lat.pstride + r) * 3, 32, ksum, upsum, eqsum, fsum);
@@ -920,13 +935,13 @@ __global__ __launch_bounds__(256) void pack_bits_kernel(Lattice lat) {
     const uint8_t *src = lat.spins + (size_t)e * 32u;       // [r][c][32w..] matches the byte layout
     uint32_t v = 0;
 #pragma unroll
-    for (uint32_t q = 0; q < 32; ++q) v |= (uint32_t)(src[q] & 1u) << q;
+    for (uint32_t i = 0; i < 32; ++i) v |= (uint32_t)(src[i] & 1u) << bit_of_index(i);
     lat.bits[e] = v;
     if (e < 2u * W1 && lat.kind == 0) {
         uint32_t f = 0;
         const uint8_t *fb = lat.fbits + (size_t)e * 32u;
 #pragma unroll
-        for (uint32_t q = 0; q < 32; ++q) f |= (uint32_t)((fb[q] >> 2) & 1u) << q;
+        for (uint32_t i = 0; i < 32; ++i) f |= (uint32_t)((fb[i] >> 2) & 1u) << bit_of_index(i);
         ((uint32_t *)lat.fbw)[e] = f;
     }
 }
@@ -938,7 +953,7 @@ __global__ __launch_bounds__(256) void unpack_bits_kernel(Lattice lat) {
     const uint32_t v = lat.bits[e];
     uint8_t *dst = lat.spins + (size_t)e * 32u;
 #pragma unroll
-    for (uint32_t q = 0; q < 32; ++q) dst[q] = (uint8_t)((v >> q) & 1u);
+    for (uint32_t i = 0; i < 32; ++i) dst[i] = (uint8_t)((v >> bit_of_index(i)) & 1u);
 }
 
 // ---------------------------------------------------------------------
