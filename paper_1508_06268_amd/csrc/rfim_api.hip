@@ -1544,7 +1544,10 @@ int ensure_side_streams(rfim_batch *b, int n) {
     while ((int)b->aux.size() < n) {
         hipStream_t q = nullptr;
         hipEvent_t e = nullptr;
-        HIPCHK(create_lane_stream(&q));
+        // plain streams: lanes of a batch made right after many short-lived
+        // batches (the autotuner's probes) ran ~30 % slower on CU-masked
+        // queues of their own
+        HIPCHK(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
         b->aux.push_back(q);
         HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         b->ev_join.push_back(e);
