@@ -162,6 +162,24 @@ def kernel_only(torch, P, W, sweeps, storage):
                                                                  "bits" if storage else "bytes"))
 
 
+def gauss_kernel_only(torch, P, W, which, sweeps=20):
+    """Only a continuous-field sweep, for counters: `streaming` is L=64,
+    R=128 (Gaussian fields, h=2) on one stream, `resident` the paper-scale
+    shape L=32, R=64 on its default LDS-resident launch; `sweeps` sweeps
+    with an exchange every 10."""
+    if which == "streaming":
+        L, R = 64, 128
+    else:
+        L, R = 32, 64
+    stream = torch.cuda.Stream()
+    h = P.Rfim(L, R, 1.0, 2.0, W.gaussian_fields(L, [5, L]), W.geometric_temps(R, 1.0, 6.0), seed=5,
+               stream=stream)
+    h.set_concurrency(1)
+    h.sweep(sweeps, 10)
+    h.synchronize()
+    log("gauss %s mode: L=%d R=%d shape %s, %d sweeps" % (which, L, R, h.launch_shape(), sweeps))
+
+
 def hbm_bits_leg(torch, P, W, n=128, R=128, sweeps=100, every=10):
     """One bit per spin on data of the HBM-streaming leg's byte size: n
     realizations x R=128 at L=64 (512 MiB of spin bits at n = 128), each a
@@ -526,8 +544,11 @@ def main():
                     help="served_stream: only the continuous-batching serving run (its own JSON line)")
     ap.add_argument("--production-sweeps", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="bench", choices=["bench", "kernel", "kernel_bits", "tiles", "streaming", "copy"],
-                    help="kernel / kernel_bits: only the byte / bit sweep kernel (for counters); tiles: only "
+    ap.add_argument("--mode", default="bench", choices=["bench", "kernel", "kernel_bits", "kernel_gauss", "resident_gauss", "tiles",
+                                                     "streaming", "copy"],
+                    help="kernel / kernel_bits: only the byte / bit sweep kernel (for counters); kernel_gauss / "
+                         "resident_gauss: only the continuous-field streaming (L=64, R=128) / LDS-resident "
+                         "(L=32, R=64) sweep; tiles: only "
                          "the multi-hit "
                          "tile kernel (for counters); streaming: only the "
                          "HBM-streaming leg; copy: a plain copy of --copy-bytes (counter calibration)")
@@ -572,6 +593,9 @@ def main():
     torch.cuda.set_device(0)
     if args.mode in ("kernel", "kernel_bits"):
         kernel_only(torch, P, W, 20, P.rfim.SPINS_BITS if args.mode == "kernel_bits" else P.rfim.SPINS_BYTES)
+        return
+    if args.mode in ("kernel_gauss", "resident_gauss"):
+        gauss_kernel_only(torch, P, W, "streaming" if args.mode == "kernel_gauss" else "resident")
         return
     if args.mode == "tiles":
         tiles_only(torch, P, W)

@@ -102,9 +102,11 @@ typedef struct rfim_params {
  * free(ptr, ctx) takes back a pointer alloc returned, after the handle's
  * work on it has finished.  Both run on the thread that called into the
  * library (create, rfim_set_measure, destroy).  A handle asks for one block
- * at create time (all its buffers) and three more when rfim_set_measure
- * first turns the measurement on.  A caching allocator (e.g. PyTorch's) can
- * serve them. */
+ * at create time (all its buffers), at most two more for its default
+ * storage and shape (the bit arrays of +-1 fields at L = 64..256, the second
+ * spin buffer of a slab shape), one when a slab shape is first set, two for
+ * bit storage, and three when rfim_set_measure first turns the measurement
+ * on.  A caching allocator (e.g. PyTorch's) can serve them. */
 typedef struct rfim_alloc {
     void *(*alloc)(size_t bytes, void *ctx);
     void (*free)(void *ptr, void *ctx);
@@ -213,9 +215,21 @@ int rfim_fourier(rfim_t *h, double *fourier);
  * most one row: 4 nw <= L/2) per thread and wg in {64, 128, 256} threads
  * per workgroup; mode 1 (L <= 32, nw <= 4)
  * keeps each replica in one workgroup's LDS (wg in {64, ..., 1024}) for all
- * sweeps of an exchange interval.  Other L have the single shape (0, 0, 0).
+ * sweeps of an exchange interval.  Modes 2..4 (L = 16 or 32, standalone
+ * handles only) cut each replica along z into nw in {2, 4, 8} slabs, one
+ * workgroup each (wg in {128, ..., 1024}), so that few replicas still
+ * cover every CU: a launch runs up to mode - 1 sweeps in LDS on the slab
+ * and 2 (mode - 1) halo planes per side, recomputing the halo instead of
+ * waiting for the neighbouring workgroups; the slab must be at least two
+ * planes thick, the box (slab plus halos) at most L planes and 64 KB, and
+ * the box at most 2 wg work items of 8 sites.  The first slab shape set on
+ * a handle allocates a second spin buffer of R_cap * L^3 bytes
+ * (RFIM_ENOMEM if that fails).  Other L have the single shape (0, 0, 0).
  * A new handle starts from a shape chosen by L from measurements on gfx950
- * (rfim_get_launch_shape reports it).
+ * (rfim_get_launch_shape reports it): (1, 1, 64), (1, 2, 256), (1, 4, 1024)
+ * at L = 8, 16, 32, (0, 4, 128) above; a standalone handle with continuous
+ * fields at L = 32 and R_cap <= 64 starts on the slab shape (3, 4, 1024)
+ * when its second spin buffer can be allocated.
  * RFIM_EINVAL for a shape not valid for the handle's L. */
 int rfim_set_launch_shape(rfim_t *h, int mode, int nw, int wg);
 int rfim_get_launch_shape(const rfim_t *h, int *mode, int *nw, int *wg);

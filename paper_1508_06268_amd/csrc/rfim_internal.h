@@ -73,10 +73,11 @@ struct Lattice {
 constexpr int kMaxFusedBlocks = 1024;
 
 // Launch shapes.  Power-of-two L >= 8: mode 0 (streaming: one chunk of
-// nw dwords per thread, wg in {64, 128, 256}) or mode 1 (LDS-resident,
+// nw dwords per thread, wg in {64, 128, 256}), mode 1 (LDS-resident,
 // L <= 32: one workgroup of wg threads per replica runs every sweep of an
-// exchange interval).  Other L: generic kernel, shape (0, 0, 0).  Every
-// shape gives bit-identical results.
+// exchange interval) or modes 2..4 (slabs, L = 16..64: nw slabs per
+// replica, mode - 1 sweeps per launch, wg threads).  Other L: generic
+// kernel, shape (0, 0, 0).  Every shape gives bit-identical results.
 bool shape_valid(int L, int mode, int nw, int wg);
 // Energy partials per replica for a shape (1 for resident, the workgroups
 // per replica when the streaming sweep fuses the energy, else 64).
@@ -100,6 +101,16 @@ struct Launch {
     const Lattice *single = nullptr;
     int r0 = 0;
 };
+
+// Slab sweeps (mode 2..4, L = 16 or 32): nslab workgroups per replica, each
+// a z-slab of L/nslab planes with the halo recomputed, mode - 1 sweeps per
+// launch at most; reads `src`, writes `dst` (a second spin buffer: the
+// workgroups of a replica must not see each other's new planes).
+int slab_sweeps_per_launch(int mode);
+size_t slab_lds_bytes(int L, int mode, int nslab);
+int slab_positions_per_thread(int L, int mode, int nslab, int wg);
+hipError_t launch_slab_sweep(const Lattice &lat, const uint8_t *src, uint8_t *dst, int mode, int nslab, int wg,
+                             int nsweep, int toff, int energy, hipStream_t s);
 
 // Double-checkerboard order with multi-hit updates (Sec. 3.2, Sec. 5.2):
 // tiles of tx * ty * tz sites, `hits` local sweeps per tile visit.  Valid

@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "rfim_internal.h"
 
 namespace rfim_dev {
@@ -608,7 +610,7 @@ __global__ __launch_bounds__(256) void sweep_pow2(Lattice lat0, const Lattice *_
 // between half-sweeps), then, if asked, the energy partial of the final
 // state, and writes the spins back.  Fields stay in global memory (shared
 // by every replica, so they live in L2).
-template <int KIND, int NW, bool BATCH>
+template <int KIND, int NW, bool BATCH, bool ONE>
 __global__ __launch_bounds__(1024) void sweep_resident(Lattice lat0, const Lattice *__restrict__ lats,
                                                         const uint2 *__restrict__ map, int nsweep,
                                                         int energy) {
@@ -631,6 +633,44 @@ __global__ __launch_bounds__(1024) void sweep_resident(Lattice lat0, const Latti
     const uint32_t nchunk = half / (4u * NW);
     __syncthreads();
     const uint32_t never = KIND == 0 ? __builtin_amdgcn_readfirstlane(sthr[31]) : 0u;
+    if constexpr (ONE) {
+        // every thread owns chunk threadIdx.x of both colours: its fields
+        // are read once per launch and kept in registers
+        const uint32_t g0 = threadIdx.x * NW, j0 = 4u * g0;
+        uint32_t F4c[2][NW];
+        f32x4 HFc[2][NW];
+#pragma unroll
+        for (int col = 0; col < 2; ++col) {
+            if (KIND == 0) {
+                load_words<NW>(fbits + (size_t)col * half, j0, F4c[col]);
+            } else {
+#pragma unroll
+                for (int w = 0; w < NW; ++w)
+                    HFc[col][w] = *(GAS const f32x4 *)(fhf + (size_t)col * half + j0 + 4u * w);
+            }
+        }
+        for (int sw = 0; sw < nsweep; ++sw) {
+#pragma unroll
+            for (int col = 0; col < 2; ++col) {
+                uint8_t *own = sp + col * half;
+                const uint8_t *oth = sp + (1u - col) * half;
+                const uint32_t c1 = 2u * (t0 + (uint32_t)sw) + col;
+                ChunkIn<KIND, NW> in;
+                in.c = chunk_geometry<NW>(j0, (uint32_t)col, (uint32_t)lat.L, (uint32_t)lat.log2L, half);
+                load_words<NW>(own, j0, in.Wown);
+                load_around<NW>(oth, j0, in.c, in.a);
+                if (KIND == 1) {
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) in.HF[w] = HFc[col][w];
+                }
+                uint32_t W[NW], U[NW], Wnew[NW];
+                const uint32_t any = chunk_flip_any<KIND, NW>(lat, sthr, never, in, F4c[col], g0, c1, r, beta, W,
+                                                              U, Wnew);
+                if (any) store_words<NW>(own, j0, Wnew);
+                __syncthreads();
+            }
+        }
+    } else {
     for (int sw = 0; sw < nsweep; ++sw) {
         for (uint32_t col = 0; col < 2; ++col) {
             uint8_t *own = sp + col * half;
@@ -646,6 +686,7 @@ __global__ __launch_bounds__(1024) void sweep_resident(Lattice lat0, const Latti
             }
             __syncthreads();
         }
+    }
     }
     if (energy) {
         int ksum = 0, upsum = 0, eqsum = 0;
@@ -667,6 +708,175 @@ __global__ __launch_bounds__(1024) void sweep_resident(Lattice lat0, const Latti
     }
     GAS u32x4 *dst = (GAS u32x4 *)(gptr(lat.spins) + (size_t)r * N);
     for (uint32_t q = threadIdx.x; q < N / 16u; q += blockDim.x) dst[q] = lds4[q];
+}
+
+// ---------------------------------------------------------------------
+// Slab sweeps (L = 16 or 32): each replica is cut along z into S slabs of
+// L/S planes, one workgroup per (replica, slab), so that a few replicas
+// still fill every CU.  A launch runs `nsweep` whole sweeps of the plain
+// order: the workgroup stages its slab and 2 nsweep halo planes on each
+// side (both colours) in LDS and runs the 2 nsweep half-sweeps there,
+// half-sweep s updating the planes [s + 1, P - 1 - s) of the box; the
+// outer planes it updates are other slabs', recomputed here from the same
+// inputs and the same random words, so the slab's own planes end exactly
+// as in the plain sweep and no workgroup waits for another.  The slab goes
+// to `dst` (reading from `src`: a workgroup must not see a neighbour's new
+// planes), and with `energy` the workgroup writes the energy partial of
+// its slab.
+//
+// Work item: SW dwords (4 SW sites) of one row of one colour.  Thread t
+// owns the box positions t, t + blockDim, ... (NP of them) for the whole
+// launch and keeps their fields, both colours, in registers; a position is
+// updated at the half-steps whose plane range holds it.  A plane has
+// L * L / (8 SW) items: at L = 32 a wave's positions share one plane, so
+// the test is uniform per wave.
+// ---------------------------------------------------------------------
+template <int KIND, int NP>
+__global__ __launch_bounds__(1024) void sweep_slabs(Lattice lat, const uint8_t *__restrict__ src,
+                                                     uint8_t *__restrict__ dst, int S, int nsweep, int toff,
+                                                     int energy) {
+    constexpr int SW = 2;
+    extern __shared__ uint4 lds_raw[];
+    __shared__ uint32_t sthr[32];
+    uint8_t *box = (uint8_t *)lds_raw;                     // [P][2][plane]
+    const uint32_t L = (uint32_t)lat.L, half = (uint32_t)lat.half;
+    const uint32_t rowb = L >> 1;                          // bytes per row of one colour
+    const uint32_t nwr = L >> 3;                           // dwords per row of one colour
+    const uint32_t lipr = (uint32_t)lat.log2L - 4u;        // log2 of items per row (nwr / SW)
+    const uint32_t ipr = 1u << lipr;
+    const uint32_t plane = L * rowb;                       // bytes per plane of one colour
+    const uint32_t ipp = L << lipr;                        // items per plane
+    const uint32_t slab = L / (uint32_t)S;
+    const uint32_t H = 2u * (uint32_t)nsweep;
+    const uint32_t P = slab + 2u * H;
+    const uint32_t r = blockIdx.x / (uint32_t)S, sl = blockIdx.x % (uint32_t)S;
+    const uint32_t z0 = sl * slab;
+    GAS const uint8_t *rsrc = gptr(src) + (size_t)r * lat.N;
+    const int slot = gptr(lat.r2t)[r];
+    const float beta = KIND == 1 ? gptr(lat.betaf)[slot] : 0.0f;
+    const uint32_t t0 = (uint32_t)(gptr(lat.ctrs)[0] + (uint64_t)toff);
+    GAS const uint8_t *fbits = gptr(lat.fbits);
+    GAS const float *fhf = gptr(lat.fhf), *fraw = gptr(lat.fraw);
+    // the positions of this thread and their fields (issued first, so the
+    // field loads overlap the staging loads)
+    uint32_t pb[NP], py[NP], pz[NP], pw[NP];
+    uint32_t F4c[2][NP][SW];
+    f32x4 HFc[2][NP][SW];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const uint32_t pos = threadIdx.x + (uint32_t)k * blockDim.x;
+        const uint32_t rem = pos & (ipp - 1u);
+        pb[k] = pos / ipp;                                 // P or more when the position is past the box
+        py[k] = rem >> lipr;
+        pw[k] = SW * (rem & (ipr - 1u));
+        pz[k] = (z0 + L - H + pb[k]) & (L - 1u);
+        const uint32_t j0 = (pz[k] * L + py[k]) * rowb + 4u * pw[k];
+        if (pb[k] < P) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                if (KIND == 0) {
+                    load_words<SW>(fbits + (size_t)c * half, j0, F4c[c][k]);
+                } else {
+#pragma unroll
+                    for (int w = 0; w < SW; ++w)
+                        HFc[c][k][w] = *(GAS const f32x4 *)(fhf + (size_t)c * half + j0 + 4u * w);
+                }
+            }
+        }
+    }
+    // stage the box, 16 bytes at a time: plane b of the box is z0 - H + b
+    const uint32_t per_plane16 = plane >> 4;
+    const uint32_t n16 = P * 2u * per_plane16;
+    for (uint32_t e = threadIdx.x; e < n16; e += blockDim.x) {
+        const uint32_t q = e % per_plane16, bc = e / per_plane16;   // bc = 2 b + c
+        const uint32_t b = bc >> 1, c = bc & 1u;
+        const uint32_t zg = (z0 + L - H + b) & (L - 1u);
+        ((u32x4 *)box)[e] = *(GAS const u32x4 *)(rsrc + (size_t)c * half + (size_t)zg * plane + 16u * q);
+    }
+    if (KIND == 0 && threadIdx.x < 32u) sthr[threadIdx.x] = gptr(lat.thr)[slot * 32 + threadIdx.x];
+    const uint32_t *bw = (const uint32_t *)box;
+    const uint32_t ppw = plane >> 2;                       // dwords per colour-plane
+    __syncthreads();
+    const uint32_t never = KIND == 0 ? __builtin_amdgcn_readfirstlane(sthr[31]) : 0u;
+    for (int sw = 0; sw < nsweep; ++sw) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const uint32_t st = 2u * (uint32_t)sw + (uint32_t)c;
+            const uint32_t c1 = 2u * (t0 + (uint32_t)sw) + (uint32_t)c;
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                if (pb[k] >= st + 1u && pb[k] + 1u + st < P) {
+                    const uint32_t b = pb[k], y = py[k], w0 = pw[k], zg = pz[k];
+                    const uint32_t rown = (2u * b + (uint32_t)c) * ppw + y * nwr;
+                    const uint32_t oth = (2u * b + 1u - (uint32_t)c) * ppw;
+                    ChunkIn<KIND, SW> in;
+                    in.c.p = ((uint32_t)c + y + zg) & 1u;
+#pragma unroll
+                    for (int w = 0; w < SW; ++w) {
+                        in.Wown[w] = bw[rown + w0 + w];
+                        in.a.W[w] = bw[oth + y * nwr + w0 + w];
+                        in.a.Wyp[w] = bw[oth + ((y + 1u) & (L - 1u)) * nwr + w0 + w];
+                        in.a.Wym[w] = bw[oth + ((y - 1u) & (L - 1u)) * nwr + w0 + w];
+                        in.a.Wzp[w] = bw[oth + 2u * ppw + y * nwr + w0 + w];
+                        in.a.Wzm[w] = bw[oth - 2u * ppw + y * nwr + w0 + w];
+                        if (KIND == 1) in.HF[w] = HFc[c][k][w];
+                    }
+                    in.a.Wx = bw[oth + y * nwr + ((w0 + (in.c.p ? (uint32_t)SW : nwr - 1u)) & (nwr - 1u))];
+                    const uint32_t g0 = ((pz[k] * L + y) * rowb >> 2) + w0;
+                    uint32_t W[SW], U[SW], Wnew[SW];
+                    const uint32_t any = chunk_flip_any<KIND, SW>(lat, sthr, never, in, F4c[c][k], g0, c1, r, beta,
+                                                                  W, U, Wnew);
+                    if (any) {
+#pragma unroll
+                        for (int w = 0; w < SW; ++w) ((uint32_t *)box)[rown + w0 + w] = Wnew[w];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (energy) {
+        // the slab's colour-1 items against the final colour-0 planes (the
+        // last colour-0 half-sweep covered the slab and one plane each side)
+        int ksum = 0, upsum = 0, eqsum = 0, nch = 0;
+        double fsum = 0.0;
+        for (uint32_t it = threadIdx.x; it < slab * ipp; it += blockDim.x, ++nch) {
+            const uint32_t bs = it >> ((uint32_t)lat.log2L + lipr), rem = it & (ipp - 1u);
+            const uint32_t b = H + bs, y = rem >> lipr, w0 = SW * (rem & (ipr - 1u));
+            const uint32_t zg = z0 + bs;
+            const uint32_t j0 = (zg * L + y) * rowb + 4u * w0;
+            const uint32_t o0 = (2u * b) * ppw;
+            Around<SW> a;
+            Chunk cg;
+            cg.p = (1u + y + zg) & 1u;
+            uint32_t S1[SW], U[SW], F1[SW];
+#pragma unroll
+            for (int w = 0; w < SW; ++w) {
+                a.W[w] = bw[o0 + y * nwr + w0 + w];
+                a.Wyp[w] = bw[o0 + ((y + 1u) & (L - 1u)) * nwr + w0 + w];
+                a.Wym[w] = bw[o0 + ((y - 1u) & (L - 1u)) * nwr + w0 + w];
+                a.Wzp[w] = bw[o0 + 2u * ppw + y * nwr + w0 + w];
+                a.Wzm[w] = bw[o0 - 2u * ppw + y * nwr + w0 + w];
+                S1[w] = bw[(2u * b + 1u) * ppw + y * nwr + w0 + w];
+                F1[w] = 0u;
+            }
+            a.Wx = bw[o0 + y * nwr + ((w0 + (cg.p ? (uint32_t)SW : nwr - 1u)) & (nwr - 1u))];
+            neighbour_sums<SW>(cg, a, U);
+            if (KIND == 0) load_words<SW>(fbits + half, j0, F1);
+            chunk_energy<KIND, SW>(lat, S1, a.W, U, F1, fbits, fraw + half, fraw, j0, ksum, upsum, eqsum, fsum);
+        }
+        block_partial<KIND>(gptr(lat.part) + ((size_t)sl * lat.pstride + r) * 3, 4 * SW * nch, ksum, upsum, eqsum,
+                            fsum);
+    }
+    // the slab's planes, both colours
+    GAS uint8_t *rdst = gptr(dst) + (size_t)r * lat.N;
+    const uint32_t m16 = slab * 2u * per_plane16;
+    for (uint32_t e = threadIdx.x; e < m16; e += blockDim.x) {
+        const uint32_t q = e % per_plane16, bc = e / per_plane16;
+        const uint32_t bs = bc >> 1, c = bc & 1u;
+        *(GAS u32x4 *)(rdst + (size_t)c * half + (size_t)(z0 + bs) * plane + 16u * q) =
+            ((const u32x4 *)box)[(2u * (H + bs) + c) * per_plane16 + q];
+    }
 }
 
 // ---------------------------------------------------------------------
@@ -1224,6 +1434,16 @@ __global__ void advance_kernel(uint64_t *ctrs, int tadv) {
 bool shape_valid(int L, int mode, int nw, int wg) {
     const bool pow2 = L >= 8 && (L & (L - 1)) == 0;
     if (!pow2) return mode == 0 && nw == 0 && wg == 0;      // generic kernel, fixed shape
+    if (mode >= 2 && mode <= 4) {
+        // slabs: nw = slabs per replica, mode - 1 sweeps per launch
+        if (L != 16 && L != 32) return false;
+        if (nw != 2 && nw != 4 && nw != 8) return false;
+        if (L / nw < 2) return false;
+        if (L / nw + 4 * slab_sweeps_per_launch(mode) > L) return false;   // the box must not wrap onto itself
+        if (slab_lds_bytes(L, mode, nw) > 65536) return false;
+        if (wg != 128 && wg != 256 && wg != 512 && wg != 1024) return false;
+        return slab_positions_per_thread(L, mode, nw, wg) <= 2;
+    }
     if (nw != 1 && nw != 2 && nw != 4 && nw != 8) return false;
     if (4 * nw > L / 2) return false;                        // a chunk lies inside one row
     const long long chunks = (long long)L * L * L / 8 / nw;  // per colour and replica
@@ -1247,6 +1467,7 @@ int blocks_per_replica(int L, int mode, int nw, int wg) {
         return (int)(nb < 1 ? 1 : nb);
     }
     if (mode == 1) return 1;
+    if (mode >= 2) return nw;                                // one partial per slab
     const long long chunks = (long long)L * L * L / 8 / nw;
     if (chunks < wg) return 1;
     const long long nb = chunks / wg;
@@ -1261,7 +1482,7 @@ int stream_blocks_per_replica(int L, int nw, int wg) {
 
 bool fused_energy(const Lattice &lat) {
     if (lat.log2L < 3) return false;
-    if (lat.mode == 1) return true;
+    if (lat.mode >= 1) return true;
     const long long chunks = (long long)lat.N / 8 / lat.nw;
     return chunks <= (long long)lat.wg * kMaxFusedBlocks;
 }
@@ -1298,19 +1519,72 @@ static void launch_pow2(const Launch &ln, const Lattice &lat0, int colour, int t
                            toff, remap, lwpr, ln.r0);
 }
 
-template <int KIND, bool BATCH>
-static void launch_res(const Launch &ln, const Lattice &lat0, int nsweep, int energy, hipStream_t s) {
+// Workgroups of `kernel` one CU holds at once (0 if unknown), cached in
+// `slot` (-1: not asked yet), and the current device's CU count.
+static int resident_blocks_per_cu(std::atomic<int> &slot, const void *kernel, int wg, size_t lds) {
+    int n = slot.load(std::memory_order_relaxed);
+    if (n >= 0) return n;
+    n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, wg, lds) != hipSuccess) {
+        (void)hipGetLastError();
+        n = 0;
+    }
+    slot.store(n, std::memory_order_relaxed);
+    return n;
+}
+
+static int device_cus() {
+    static std::atomic<int> cache[16] = {};
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    if (dev >= 0 && dev < 16 && (n = cache[dev].load(std::memory_order_relaxed)) > 0) return n;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    if (dev >= 0 && dev < 16) cache[dev].store(n, std::memory_order_relaxed);
+    return n;
+}
+
+template <int KIND, int NW, bool BATCH>
+static void launch_res_nw(const Launch &ln, const Lattice &lat0, int nsweep, int energy, hipStream_t s) {
     const size_t lds = (size_t)ln.L * ln.L * ln.L;
     const dim3 grid(ln.nblocks), block(ln.wg);
-    if (ln.nw == 4)
-        hipLaunchKernelGGL((sweep_resident<KIND, 4, BATCH>), grid, block, lds, s, lat0, ln.lats, ln.map, nsweep,
-                           energy);
-    else if (ln.nw == 2)
-        hipLaunchKernelGGL((sweep_resident<KIND, 2, BATCH>), grid, block, lds, s, lat0, ln.lats, ln.map, nsweep,
-                           energy);
+    // one chunk per thread and colour: the register-field form, unless its
+    // extra registers would leave fewer workgroups per CU than the plain
+    // form while there are more workgroups than the device holds at once
+    bool one = (long long)ln.L * ln.L * ln.L / 8 / NW == ln.wg;
+    if (one) {
+        // per instantiation, (L, wg) is fixed by chunks == wg up to the two
+        // L of NW = 1; index the cache by L
+        static std::atomic<int> occ[2][6] = {{-1, -1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1, -1}};
+        const int li = ln.L == 8 ? 0 : (ln.L == 16 ? 1 : (ln.L == 32 ? 2 : 3));
+        const int b1 = resident_blocks_per_cu(occ[1][li], (const void *)sweep_resident<KIND, NW, BATCH, true>,
+                                              ln.wg, lds);
+        const int b0 = resident_blocks_per_cu(occ[0][li], (const void *)sweep_resident<KIND, NW, BATCH, false>,
+                                              ln.wg, lds);
+        const long long cus = device_cus();
+        if (b1 < b0 && (long long)ln.nblocks > cus * b1) one = false;
+    }
+    if (one)
+        hipLaunchKernelGGL((sweep_resident<KIND, NW, BATCH, true>), grid, block, lds, s, lat0, ln.lats, ln.map,
+                           nsweep, energy);
     else
-        hipLaunchKernelGGL((sweep_resident<KIND, 1, BATCH>), grid, block, lds, s, lat0, ln.lats, ln.map, nsweep,
-                           energy);
+        hipLaunchKernelGGL((sweep_resident<KIND, NW, BATCH, false>), grid, block, lds, s, lat0, ln.lats, ln.map,
+                           nsweep, energy);
+}
+
+template <int KIND, bool BATCH>
+static void launch_res(const Launch &ln, const Lattice &lat0, int nsweep, int energy, hipStream_t s) {
+    if (ln.nw == 4)
+        launch_res_nw<KIND, 4, BATCH>(ln, lat0, nsweep, energy, s);
+    else if (ln.nw == 2)
+        launch_res_nw<KIND, 2, BATCH>(ln, lat0, nsweep, energy, s);
+    else
+        launch_res_nw<KIND, 1, BATCH>(ln, lat0, nsweep, energy, s);
 }
 
 hipError_t launch_stream_sweep(const Launch &ln, int colour, int toff, int energy, hipStream_t s) {
@@ -1344,6 +1618,40 @@ hipError_t launch_generic_sweep(const Lattice &lat, int colour, int toff, hipStr
         hipLaunchKernelGGL(sweep_generic<0>, grid, dim3(256), 0, s, lat, colour, toff);
     else
         hipLaunchKernelGGL(sweep_generic<1>, grid, dim3(256), 0, s, lat, colour, toff);
+    return hipGetLastError();
+}
+
+int slab_sweeps_per_launch(int mode) { return mode >= 2 ? mode - 1 : 0; }
+
+size_t slab_lds_bytes(int L, int mode, int nslab) {
+    const int P = L / nslab + 4 * slab_sweeps_per_launch(mode);
+    return (size_t)P * (size_t)L * L;          // both colours: L^2 / 2 bytes each
+}
+
+int slab_positions_per_thread(int L, int mode, int nslab, int wg) {
+    const long long items = (long long)(L / nslab + 4 * slab_sweeps_per_launch(mode)) * L * L / 16;
+    return (int)((items + wg - 1) / wg);
+}
+
+template <int KIND>
+static void launch_slab_kind(const Lattice &lat, const uint8_t *src, uint8_t *dst, int np, int nslab, int wg,
+                             size_t lds, int nsweep, int toff, int energy, hipStream_t s) {
+    const dim3 grid((unsigned)(lat.R * nslab)), block((unsigned)wg);
+    if (np == 1)
+        hipLaunchKernelGGL((sweep_slabs<KIND, 1>), grid, block, lds, s, lat, src, dst, nslab, nsweep, toff, energy);
+    else
+        hipLaunchKernelGGL((sweep_slabs<KIND, 2>), grid, block, lds, s, lat, src, dst, nslab, nsweep, toff, energy);
+}
+
+hipError_t launch_slab_sweep(const Lattice &lat, const uint8_t *src, uint8_t *dst, int mode, int nslab, int wg,
+                             int nsweep, int toff, int energy, hipStream_t s) {
+    const size_t lds = slab_lds_bytes(lat.L, mode, nslab);
+    const int np = slab_positions_per_thread(lat.L, mode, nslab, wg);
+    if (np < 1 || np > 2 || nsweep < 1 || nsweep > slab_sweeps_per_launch(mode)) return hipErrorInvalidValue;
+    if (lat.kind == 0)
+        launch_slab_kind<0>(lat, src, dst, np, nslab, wg, lds, nsweep, toff, energy, s);
+    else
+        launch_slab_kind<1>(lat, src, dst, np, nslab, wg, lds, nsweep, toff, energy, s);
     return hipGetLastError();
 }
 

@@ -47,7 +47,7 @@ def test_energies_consistent_with_oracle_components(rfim_mod, oracle_mod):
     assert np.allclose(gf, of, rtol=1e-12, atol=1e-9)
 
 
-def _gpu_time_averages(rfim_mod, case, seeds, concurrency=0):
+def _gpu_time_averages(rfim_mod, case, seeds, concurrency=0, shape=None):
     """Per-seed time averages of E and |M| by slot over the measurement
     window of a case (same protocol as the oracle fixture: burn sweeps with
     an exchange every 10, then one sample after every exchange step of the
@@ -59,6 +59,8 @@ def _gpu_time_averages(rfim_mod, case, seeds, concurrency=0):
     E, A = [], []
     for seed in seeds:
         g = rfim_mod.Rfim(c["L"], c["R"], c["J"], c["h"], f, T, seed=seed)
+        if shape is not None:
+            g.set_launch_shape(*shape)
         if concurrency:
             g.set_concurrency(concurrency)
         g.sweep(c["burn"], c["every"])
@@ -72,11 +74,12 @@ def _gpu_time_averages(rfim_mod, case, seeds, concurrency=0):
     return np.array(E), np.array(A)
 
 
-@pytest.mark.parametrize("case,set_name,concurrency", [
-    ("l32", "l32_null", 0),      # L=32, R=64: the LDS-resident default shape
-    ("l64", "l64_null", 2),      # L=64, R=8: streaming half-sweeps on two streams
+@pytest.mark.parametrize("case,set_name,concurrency,shape", [
+    ("l32", "l32_null", 0, None),            # L=32, R=64: the default slab shape
+    ("l32", "l32_null", 0, (1, 4, 1024)),    # the LDS-resident shape
+    ("l64", "l64_null", 2, None),            # L=64, R=8: streaming half-sweeps on two streams
 ])
-def test_statistics_over_seeds(rfim_mod, case, set_name, concurrency):
+def test_statistics_over_seeds(rfim_mod, case, set_name, concurrency, shape):
     """32 GPU seeds against 32 disjoint oracle seeds (stored statistics from
     tests/golden/make_gaussian_stats.py): per slot, Welch's t on the
     time-averaged energy and |M|; the family of 2R comparisons must pass at
@@ -91,7 +94,7 @@ def test_statistics_over_seeds(rfim_mod, case, set_name, concurrency):
     here = os.path.dirname(os.path.abspath(__file__))
     d = json.load(open(os.path.join(here, "golden", "gaussian_two_sample.json")))
     ref = d["sets"][set_name]
-    E, A = _gpu_time_averages(rfim_mod, case, range(1000, 1000 + d["nseeds"]), concurrency)
+    E, A = _gpu_time_averages(rfim_mod, case, range(1000, 1000 + d["nseeds"]), concurrency, shape)
     reject, pmin, thr, tmax = compare(summary(E), summary(A), from_json(ref["E"]), from_json(ref["absM"]))
     print("%s: GPU vs oracle seeds, p_min %.3g (threshold %.3g), max |t| %.2f" % (case, pmin, thr, tmax))
     assert not reject, (pmin, thr, tmax)
