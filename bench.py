@@ -164,9 +164,10 @@ def kernel_only(torch, P, W, sweeps, storage):
 
 def gauss_kernel_only(torch, P, W, which, sweeps=20):
     """Only a continuous-field sweep, for counters: `streaming` is L=64,
-    R=128 (Gaussian fields, h=2) on one stream, `resident` the paper-scale
-    shape L=32, R=64 on its default LDS-resident launch; `sweeps` sweeps
-    with an exchange every 10."""
+    R=128 (Gaussian fields, h=2) on one stream, `paper_scale` the L=32,
+    R=64 shape on its default slab launch, `resident` the same on the
+    LDS-resident launch (1, 4, 1024); `sweeps` sweeps with an exchange
+    every 10."""
     if which == "streaming":
         L, R = 64, 128
     else:
@@ -174,6 +175,8 @@ def gauss_kernel_only(torch, P, W, which, sweeps=20):
     stream = torch.cuda.Stream()
     h = P.Rfim(L, R, 1.0, 2.0, W.gaussian_fields(L, [5, L]), W.geometric_temps(R, 1.0, 6.0), seed=5,
                stream=stream)
+    if which == "resident":
+        h.set_launch_shape(1, 4, 1024)
     h.set_concurrency(1)
     h.sweep(sweeps, 10)
     h.synchronize()
@@ -544,11 +547,13 @@ def main():
                     help="served_stream: only the continuous-batching serving run (its own JSON line)")
     ap.add_argument("--production-sweeps", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="bench", choices=["bench", "kernel", "kernel_bits", "kernel_gauss", "resident_gauss", "tiles",
+    ap.add_argument("--mode", default="bench", choices=["bench", "kernel", "kernel_bits", "kernel_gauss",
+                                                     "paper_scale_gauss", "resident_gauss", "tiles",
                                                      "streaming", "copy"],
                     help="kernel / kernel_bits: only the byte / bit sweep kernel (for counters); kernel_gauss / "
-                         "resident_gauss: only the continuous-field streaming (L=64, R=128) / LDS-resident "
-                         "(L=32, R=64) sweep; tiles: only "
+                         "paper_scale_gauss / resident_gauss: only the continuous-field streaming sweep (L=64, "
+                         "R=128) / the L=32, R=64 sweep on its default slab shape / on the LDS-resident shape; "
+                         "tiles: only "
                          "the multi-hit "
                          "tile kernel (for counters); streaming: only the "
                          "HBM-streaming leg; copy: a plain copy of --copy-bytes (counter calibration)")
@@ -594,8 +599,9 @@ def main():
     if args.mode in ("kernel", "kernel_bits"):
         kernel_only(torch, P, W, 20, P.rfim.SPINS_BITS if args.mode == "kernel_bits" else P.rfim.SPINS_BYTES)
         return
-    if args.mode in ("kernel_gauss", "resident_gauss"):
-        gauss_kernel_only(torch, P, W, "streaming" if args.mode == "kernel_gauss" else "resident")
+    if args.mode in ("kernel_gauss", "paper_scale_gauss", "resident_gauss"):
+        gauss_kernel_only(torch, P, W, {"kernel_gauss": "streaming", "paper_scale_gauss": "paper_scale",
+                                        "resident_gauss": "resident"}[args.mode])
         return
     if args.mode == "tiles":
         tiles_only(torch, P, W)
@@ -773,10 +779,10 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(elapsed_s * 1e3 / args.steps, 3),
         "step_ms": [round(t, 2) for t in step_ms], "step_R": step_R,
         "warmup_ms": [round(t, 2) for t in warm_ms],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": "adaptive_l64", "L": w.L, "R0": w.R, "R_final": R_final,
-                   "fields": "bimodal +-1", "J": w.J, "h": w.h, "T": [1.0, 6.0],
+                   "fields": "bimodal +-1", "spin_storage": "bits", "J": w.J, "h": w.h, "T": [1.0, 6.0],
                    "trial_runs": w.adapt["trials"], "trial_sweeps": w.adapt["sweeps_per_trial"],
                    "rate_threshold": w.adapt["rate_threshold"], "R_cap": w.R_cap,
                    "production_sweeps": w.sweeps, "exchange_every": w.every,

@@ -358,44 +358,51 @@ __device__ __forceinline__ uint32_t cvt_u32_sat(float x) {
     return r;
 }
 
-// Continuous fields, one site of a packed word: the integer bound
-// floor(e^(-beta dE) 2^32), saturated, with e^(-beta dE) = 2^(s a y)
-// (a = -2 beta log2(e), y as in cont_accept, s = 2 spin - 1 taken as
-// a (2 spin - 1) by one fma).  dE <= 0 gives a power >= 1 and the bound
+// Continuous fields.  With up = number of +1 neighbours of a site and s
+// its spin bit, J n + h h_i = 2J up + (h h_i - 6J) = 2J up + hfs (the
+// second term precomputed per site), the flip costs dE = 2 (2s - 1) y with
+// y = 2J up + hfs, and e^(-beta dE) = 2^x with
+//   x = a (2s - 1) y = a (2s - 1) 2J up + a (2s - 1) hfs,  a = -2 beta log2(e).
+// The two site-independent factors depend only on (up, s) at a given
+// temperature: a per-slot LDS table holds them, entry (up << 1) | s =
+// {a (2s - 1) 2J up, a (2s - 1)}, so x costs one FMA per site.  The integer
+// bound is floor(2^x 2^32), saturated; dE <= 0 gives x >= 0 and the bound
 // 0xFFFFFFFF, which every u32 meets: one integer test u <= bound covers
 // both cases of the Metropolis rule.
-__device__ __forceinline__ uint32_t cont_bound(float up, float spin, float hfs, float twoJ, float a) {
-    const float y = fmaf(twoJ, up, hfs);
-    const float sa = fmaf(2.0f * a, spin, -a);
-    const float p = __builtin_amdgcn_exp2f(sa * y);
-    return cvt_u32_sat(p * 0x1p32f);
+__device__ __forceinline__ void cont_table_fill(uint32_t *sthr, float beta, float Jf) {
+    const uint32_t q = threadIdx.x;
+    if (q < 14u) {
+        const float a = -2.0f * 1.44269504088896341f * beta;
+        const float sa = (q & 1u) ? a : -a;
+        const float two_j_up = 2.0f * Jf * (float)(q >> 1);
+        sthr[2 * q] = __float_as_uint(sa * two_j_up);
+        sthr[2 * q + 1] = __float_as_uint(sa);
+    }
 }
 
-// Continuous fields: four sites of one Philox block; bit q set iff site q
-// flips.
-__device__ __forceinline__ uint32_t continuous_acc(uint32_t U, uint32_t Wown, const f32x4 hf, float twoJ, float a,
+// The bound of one site from its table entry (at LDS byte offset e) and hfs.
+__device__ __forceinline__ uint32_t cont_bound(const uint8_t *tb, uint32_t e, float hfs) {
+    const float2 c = *(const float2 *)(tb + e);
+    const float x = fmaf(c.y, hfs, c.x);
+    return cvt_u32_sat(__builtin_amdgcn_exp2f(x) * 0x1p32f);
+}
+
+// Continuous fields: four sites of one Philox block (up counts U and spins
+// Wown one per byte); bit q set iff site q flips.
+__device__ __forceinline__ uint32_t continuous_acc(const uint32_t *sthr, uint32_t U, uint32_t Wown, const f32x4 hf,
                                                    const Words &rw) {
-    const float up0 = (float)(U & 0xFFu), up1 = (float)((U >> 8) & 0xFFu);
-    const float up2 = (float)((U >> 16) & 0xFFu), up3 = (float)(U >> 24);
-    const float s0 = (float)(Wown & 0xFFu), s1 = (float)((Wown >> 8) & 0xFFu);
-    const float s2 = (float)((Wown >> 16) & 0xFFu), s3 = (float)(Wown >> 24);
-    const uint32_t b0 = cont_bound(up0, s0, hf.x, twoJ, a), b1 = cont_bound(up1, s1, hf.y, twoJ, a);
-    const uint32_t b2 = cont_bound(up2, s2, hf.z, twoJ, a), b3 = cont_bound(up3, s3, hf.w, twoJ, a);
+    const uint8_t *tb = (const uint8_t *)sthr;
+    const uint32_t A = (U << 4) | (Wown << 3);      // byte q: entry offset of site q
+    const uint32_t b0 = cont_bound(tb, A & 0xFFu, hf.x), b1 = cont_bound(tb, (A >> 8) & 0xFFu, hf.y);
+    const uint32_t b2 = cont_bound(tb, (A >> 16) & 0xFFu, hf.z), b3 = cont_bound(tb, A >> 24, hf.w);
     return accept_bits(rw.w0, rw.w1, rw.w2, rw.w3, b0, b1, b2, b3);
 }
 
-// Continuous fields: four sites of one Philox block.
-__device__ __forceinline__ uint32_t continuous_flips(uint32_t U, uint32_t Wown, const f32x4 hf, float twoJ,
-                                                     float a, const Words &rw) {
-    // byte-to-float conversions (one v_cvt_f32_ubyteN each)
-    const float up0 = (float)(U & 0xFFu), up1 = (float)((U >> 8) & 0xFFu);
-    const float up2 = (float)((U >> 16) & 0xFFu), up3 = (float)(U >> 24);
-    const float s0 = (float)(Wown & 0xFFu), s1 = (float)((Wown >> 8) & 0xFFu);
-    const float s2 = (float)((Wown >> 16) & 0xFFu), s3 = (float)(Wown >> 24);
-    const uint32_t b0 = cont_bound(up0, s0, hf.x, twoJ, a), b1 = cont_bound(up1, s1, hf.y, twoJ, a);
-    const uint32_t b2 = cont_bound(up2, s2, hf.z, twoJ, a), b3 = cont_bound(up3, s3, hf.w, twoJ, a);
-    const uint32_t acc = accept_bits(rw.w0, rw.w1, rw.w2, rw.w3, b0, b1, b2, b3);
-    return __umul24(acc, 0x204081u) & 0x01010101u;
+// Continuous fields: four sites of one Philox block, the flips one bit
+// per byte.
+__device__ __forceinline__ uint32_t continuous_flips(const uint32_t *sthr, uint32_t U, uint32_t Wown,
+                                                     const f32x4 hf, const Words &rw) {
+    return __umul24(continuous_acc(sthr, U, Wown, hf, rw), 0x204081u) & 0x01010101u;
 }
 
 // The words a chunk's half-sweep update reads: its own words, the
@@ -447,8 +454,7 @@ __device__ __forceinline__ uint32_t chunk_flip(const Lattice &lat, const uint32_
         if (KIND == 0) {
             fl = bimodal_flips<NEV>(sthr, U[w], in.Wown[w], F4[w], rw, never);
         } else {
-            fl = continuous_flips(U[w], in.Wown[w], in.HF[w], 2.0f * lat.Jf, -2.0f * 1.44269504088896341f * beta,
-                                  rw);
+            fl = continuous_flips(sthr, U[w], in.Wown[w], in.HF[w], rw);
         }
         any |= fl;
         Wnew[w] = in.Wown[w] ^ fl;
@@ -549,7 +555,7 @@ template <int KIND, int NW, int ENERGY, bool BATCH>
 __global__ __launch_bounds__(256) void sweep_pow2(Lattice lat0, const Lattice *__restrict__ lats,
                                                    const uint2 *__restrict__ map, int colour, int toff,
                                                    int remap, int lwpr, int r0) {
-    __shared__ uint32_t sthr[32];
+    __shared__ __align__(16) uint32_t sthr[32];   // +-1 thresholds or the continuous-field table
     uint32_t blk = blockIdx.x;
     if (remap) {
         // consecutive block ids go round-robin to the 8 XCDs; give each XCD a
@@ -586,12 +592,15 @@ __global__ __launch_bounds__(256) void sweep_pow2(Lattice lat0, const Lattice *_
     const int slot = gptr(lat.r2t)[r];
     const uint32_t t = (uint32_t)(gptr(lat.ctrs)[0] + (uint64_t)toff);
     uint32_t never = 0;
+    const float beta = KIND == 1 ? gptr(lat.betaf)[slot] : 0.0f;
     if (KIND == 0) {
         if (threadIdx.x < 32u) sthr[threadIdx.x] = gptr(lat.thr)[slot * 32 + threadIdx.x];
         __syncthreads();
         never = __builtin_amdgcn_readfirstlane(sthr[31]);
+    } else {
+        cont_table_fill(sthr, beta, lat.Jf);
+        __syncthreads();
     }
-    const float beta = KIND == 1 ? gptr(lat.betaf)[slot] : 0.0f;
     uint32_t W[NW], U[NW], Wnew[NW];
     const uint32_t any = chunk_flip_any<KIND, NW>(lat, sthr, never, in, F4, g0, 2u * t + col, r, beta, W, U, Wnew);
     if (any) store_words<NW>(own, j0, Wnew);
@@ -615,7 +624,7 @@ __global__ __launch_bounds__(1024) void sweep_resident(Lattice lat0, const Latti
                                                         const uint2 *__restrict__ map, int nsweep,
                                                         int energy) {
     extern __shared__ uint4 lds_raw[];
-    __shared__ uint32_t sthr[32];
+    __shared__ __align__(16) uint32_t sthr[32];   // +-1 thresholds or the continuous-field table
     uint8_t *sp = (uint8_t *)lds_raw;                  // [2][half]
     // batch: map entry (realization << 16 | replica, 0)
     const Lattice &lat = BATCH ? lats[map[blockIdx.x].x >> 16] : lat0;
@@ -627,6 +636,7 @@ __global__ __launch_bounds__(1024) void sweep_resident(Lattice lat0, const Latti
     for (uint32_t q = threadIdx.x; q < N / 16u; q += blockDim.x) lds4[q] = src[q];
     if (KIND == 0 && threadIdx.x < 32) sthr[threadIdx.x] = gptr(lat.thr)[slot * 32 + threadIdx.x];
     const float beta = KIND == 1 ? gptr(lat.betaf)[slot] : 0.0f;
+    if (KIND == 1) cont_table_fill(sthr, beta, lat.Jf);
     const uint32_t t0 = (uint32_t)gptr(lat.ctrs)[0];
     GAS const uint8_t *fbits = gptr(lat.fbits);
     GAS const float *fhf = gptr(lat.fhf), *fraw = gptr(lat.fraw);
@@ -737,7 +747,7 @@ __global__ __launch_bounds__(1024) void sweep_slabs(Lattice lat, const uint8_t *
                                                      int energy) {
     constexpr int SW = 2;
     extern __shared__ uint4 lds_raw[];
-    __shared__ uint32_t sthr[32];
+    __shared__ __align__(16) uint32_t sthr[32];   // +-1 thresholds or the continuous-field table
     uint8_t *box = (uint8_t *)lds_raw;                     // [P][2][plane]
     const uint32_t L = (uint32_t)lat.L, half = (uint32_t)lat.half;
     const uint32_t rowb = L >> 1;                          // bytes per row of one colour
@@ -794,6 +804,7 @@ __global__ __launch_bounds__(1024) void sweep_slabs(Lattice lat, const uint8_t *
         ((u32x4 *)box)[e] = *(GAS const u32x4 *)(rsrc + (size_t)c * half + (size_t)zg * plane + 16u * q);
     }
     if (KIND == 0 && threadIdx.x < 32u) sthr[threadIdx.x] = gptr(lat.thr)[slot * 32 + threadIdx.x];
+    if (KIND == 1) cont_table_fill(sthr, beta, lat.Jf);
     const uint32_t *bw = (const uint32_t *)box;
     const uint32_t ppw = plane >> 2;                       // dwords per colour-plane
     __syncthreads();
@@ -898,7 +909,7 @@ __global__ __launch_bounds__(1024) void sweep_slabs(Lattice lat, const uint8_t *
 template <int KIND>
 __global__ __launch_bounds__(1024) void sweep_tiles(Lattice lat, TileShape ts, int coarse, int toff) {
     extern __shared__ uint4 lds_raw[];
-    __shared__ uint32_t sthr[32];
+    __shared__ __align__(16) uint32_t sthr[32];   // +-1 thresholds or the continuous-field table
     uint8_t *box = (uint8_t *)lds_raw;
     const uint32_t L = (uint32_t)lat.L, half = (uint32_t)lat.half;
     const uint32_t tx = (uint32_t)ts.tx, ty = (uint32_t)ts.ty, tz = (uint32_t)ts.tz;
@@ -917,6 +928,7 @@ __global__ __launch_bounds__(1024) void sweep_tiles(Lattice lat, TileShape ts, i
     const int slot = gptr(lat.r2t)[r];
     if (KIND == 0 && threadIdx.x < 32u) sthr[threadIdx.x] = gptr(lat.thr)[slot * 32 + threadIdx.x];
     const float beta = KIND == 1 ? gptr(lat.betaf)[slot] : 0.0f;
+    if (KIND == 1) cont_table_fill(sthr, beta, lat.Jf);
     const uint32_t t = (uint32_t)(gptr(lat.ctrs)[0] + (uint64_t)toff);
     // stage the box: both colours, every row of the box, the tile's dwords
     // and the two halo dwords (x, y, z wrap around the periodic lattice)
@@ -1018,7 +1030,7 @@ __host__ __device__ constexpr int bits_wg(int L) { return L == 64 ? 128 : 256; }
 template <int KIND, int ENERGY>
 __global__ __launch_bounds__(kBitsThreads) void sweep_bits(Lattice lat, int colour, int toff, int r0, int lbpr,
                                                           int remap) {
-    __shared__ uint32_t sthr[32];
+    __shared__ __align__(16) uint32_t sthr[32];   // +-1 thresholds or the continuous-field table
     uint32_t blk = blockIdx.x;
     if (remap) {
         const uint32_t per = gridDim.x >> 3;
@@ -1057,12 +1069,15 @@ __global__ __launch_bounds__(kBitsThreads) void sweep_bits(Lattice lat, int colo
     const int slot = gptr(lat.r2t)[r];
     const uint32_t t = (uint32_t)(gptr(lat.ctrs)[0] + (uint64_t)toff);
     uint32_t never = 0;
+    const float beta = KIND == 1 ? gptr(lat.betaf)[slot] : 0.0f;
     if (KIND == 0) {
         if (threadIdx.x < 32u) sthr[threadIdx.x] = gptr(lat.thr)[slot * 32 + threadIdx.x];
         __syncthreads();
         never = __builtin_amdgcn_readfirstlane(sthr[31]);
+    } else {
+        cont_table_fill(sthr, beta, lat.Jf);
+        __syncthreads();
     }
-    const float beta = KIND == 1 ? gptr(lat.betaf)[slot] : 0.0f;
     // the x neighbour, index m-1 (p = 0) or m+1 (p = 1), in the interleaved
     // order: a step of one index is a step of one byte, with the carry
     // between byte 3 and byte 0 one bit along, and the end bit from the
@@ -1101,7 +1116,7 @@ __global__ __launch_bounds__(kBitsThreads) void sweep_bits(Lattice lat, int colo
                 }
             }
         } else {
-            acc = continuous_acc(Ub, Sb, HF[b], 2.0f * lat.Jf, -2.0f * 1.44269504088896341f * beta, rw);
+            acc = continuous_acc(sthr, Ub, Sb, HF[b], rw);
         }
         flips |= nibble_to_bytes(acc) << b;
     }
