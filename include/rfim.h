@@ -103,8 +103,8 @@ typedef struct rfim_params {
  * work on it has finished.  Both run on the thread that called into the
  * library (create, rfim_set_measure, destroy).  A handle asks for one block
  * at create time (all its buffers), at most two more for its default
- * storage and shape (the bit arrays of +-1 fields at L = 64..256, the second
- * spin buffer of a slab shape), one when a slab shape is first set, two for
+ * storage and shape (the bit arrays of handles that start in bits, the
+ * second spin buffer of a slab shape), one when a slab shape is first set, two for
  * bit storage, and three when rfim_set_measure first turns the measurement
  * on.  A caching allocator (e.g. PyTorch's) can serve them. */
 typedef struct rfim_alloc {
@@ -242,9 +242,9 @@ int rfim_get_launch_shape(const rfim_t *h, int *mode, int *nw, int *wg);
  * the handle stream by events around every exchange interval; the two launch
  * sequences then fill each other's start-up and drain time.  streams = 0:
  * automatic (two streams when each half holds at least 2^22 sites of one
- * colour), 1: always one stream, 2: two streams whenever R >= 2.  Only
- * streaming shapes (mode 0, power-of-two L) are affected.  RFIM_EINVAL for
- * other values. */
+ * colour, 2^23 for the bit sweep with +-1 fields), 1: always one stream, 2:
+ * two streams whenever R >= 2.  Only streaming shapes (mode 0, power-of-two
+ * L) and bit storage are affected.  RFIM_EINVAL for other values. */
 int rfim_set_concurrency(rfim_t *h, int streams);
 int rfim_get_concurrency(const rfim_t *h);
 
@@ -280,7 +280,8 @@ int rfim_get_concurrency(const rfim_t *h);
  * RFIM_ENOMEM if the bit arrays, R_cap * L^3 / 8 bytes plus L^3 / 8 for
  * +-1 fields, allocated on first use, cannot be had).  A handle made by
  * rfim_create / rfim_create_ex / rfim_load with +-1 fields at L = 64..256
- * starts in bits, every other handle in bytes; rfim_set_launch_shape (its
+ * or continuous fields at L = 128, 256 starts in bits, every other handle
+ * in bytes; rfim_set_launch_shape (its
  * shapes are the byte kernels'), rfim_set_measure with the Fourier flag and
  * rfim_set_update_order with tiles switch a handle to bytes.  Calls that
  * read or write spins (energies, spins, checkpoints, adaptive insertion)

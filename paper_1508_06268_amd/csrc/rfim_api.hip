@@ -685,8 +685,13 @@ void destroy_impl(rfim *h) {
 // Streaming sweeps of two halves of the replicas on two streams: replicas
 // never interact within an exchange interval, and the two launch sequences
 // fill each other's start-up and drain time.  Worth it only for launches
-// that are large on their own.
+// that are large on their own: from 2^22 sites of one colour per half (R >= 64
+// at L = 64) for byte spins and continuous fields, from 2^23 for the bit sweep
+// with +-1 fields, whose launches are shortest (measured on gfx950: at L = 64,
+// R = 64 one stream runs 1196 attempts/ns against 827 split, at R = 128 the
+// split wins, 1709 against 1575).
 constexpr long long kSplitMinAttempts = 1ll << 22;
+constexpr long long kSplitMinAttemptsBits = 1ll << 23;
 
 int ensure_aux(rfim *h) {
     if (h->aux && h->aux_for == h->stream) return RFIM_OK;
@@ -706,9 +711,10 @@ int sweep_impl(rfim *h, int64_t n, int every) {
     const Lattice &lat = h->lat_host;
     const rfim_dev::Launch ln = single_launch(h);
     const bool pow2 = h->log2L >= 3;
-    const bool big = (long long)(h->R / 2) * h->half >= kSplitMinAttempts;
     const bool tiled = h->order == 1;
     const bool bitsm = h->bits_mode;
+    const bool big = (long long)(h->R / 2) * h->half >=
+                     (bitsm && h->kind == 0 ? kSplitMinAttemptsBits : kSplitMinAttempts);
     const bool split = !tiled && pow2 && (bitsm || h->mode == 0) && h->R >= 2 &&
                        (h->concurrency == 2 || (h->concurrency == 0 && big));
     rfim_dev::Launch la = ln, lb = ln;
@@ -851,10 +857,13 @@ rfim_t *rfim_create_ex(const rfim_params_t *params, const rfim_alloc_t *alloc, v
         g_error = msg;
         return nullptr;
     }
-    // +-1 fields at L = 64..256 default to one bit per spin, the faster
-    // storage there (the same chain); if its arrays cannot be had the
-    // handle keeps byte spins
-    if (h->kind == 0 && rfim_dev::bits_valid(h->L) && rfim_set_spin_storage(h, RFIM_SPINS_BITS) != RFIM_OK) {
+    // +-1 fields at L = 64..256 and continuous fields at L = 128, 256
+    // default to one bit per spin, the faster storage there (the same
+    // chain; measured on gfx950, continuous fields: +26-44 % at L = 128,
+    // -7..+3 % at L = 64, which keeps bytes); if its arrays cannot be had
+    // the handle keeps byte spins
+    if (rfim_dev::bits_valid(h->L) && (h->kind == 0 || h->L >= 128) &&
+        rfim_set_spin_storage(h, RFIM_SPINS_BITS) != RFIM_OK) {
         (void)hipGetLastError();
         g_error.clear();
     }

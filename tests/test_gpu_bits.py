@@ -68,7 +68,9 @@ def test_bits_continuous_fields_equal_byte_sweep(rfim_mod, L, R):
     T = W.geometric_temps(R, 1.0, 6.0)
     a = rfim_mod.Rfim(L, R, 1.0, 2.0, f, T, seed=3)
     b = rfim_mod.Rfim(L, R, 1.0, 2.0, f, T, seed=3)
-    b.set_spin_storage(1)
+    a.set_spin_storage(rfim_mod.rfim.SPINS_BYTES)      # L = 128, 256 start in bits
+    b.set_spin_storage(rfim_mod.rfim.SPINS_BITS)
+    assert a.spin_storage() == rfim_mod.rfim.SPINS_BYTES
     a.sweep(6, 3)
     b.sweep(6, 3)
     assert np.array_equal(a.spins(), b.spins())
@@ -86,7 +88,9 @@ def test_bits_l256_equal_byte_sweep(rfim_mod):
     T = np.array([2.0, 2.00001])
     a = rfim_mod.Rfim(L, R, 1.0, 1.0, f, T, seed=9)
     b = rfim_mod.Rfim(L, R, 1.0, 1.0, f, T, seed=9)
-    b.set_spin_storage(1)
+    a.set_spin_storage(rfim_mod.rfim.SPINS_BYTES)      # +-1 fields at L = 256 start in bits
+    b.set_spin_storage(rfim_mod.rfim.SPINS_BITS)
+    assert a.spin_storage() == rfim_mod.rfim.SPINS_BYTES
     a.sweep(4, 2)
     b.sweep(4, 2)
     assert np.array_equal(a.spins(), b.spins())
@@ -107,11 +111,11 @@ def test_bits_refuse_unsupported_sizes(rfim_mod, L):
 
 
 def test_default_storage_and_switches_to_bytes(rfim_mod):
-    """+-1 fields at L = 64..256 start in bits; Gaussian fields and other L
-    in bytes; a launch shape, the Fourier measurement or the tile order
-    switch a handle to bytes."""
+    """+-1 fields at L = 64..256 and Gaussian fields at L = 128, 256 start in
+    bits; Gaussian fields at L = 64 and other L in bytes; a launch shape, the
+    Fourier measurement or the tile order switch a handle to bytes."""
     B = rfim_mod.rfim
-    for L, kind, want in ((64, "b", 1), (128, "b", 1), (64, "g", 0), (32, "b", 0)):
+    for L, kind, want in ((64, "b", 1), (128, "b", 1), (64, "g", 0), (128, "g", 1), (32, "b", 0), (32, "g", 0)):
         f = W.bimodal_fields(L, [88, L]) if kind == "b" else W.gaussian_fields(L, [88, L])
         g = rfim_mod.Rfim(L, 2, 1.0, 1.0, f, [1.0, 2.0], seed=1)
         assert g.spin_storage() == want, (L, kind)
@@ -132,3 +136,31 @@ def test_default_storage_and_switches_to_bytes(rfim_mod):
             with pytest.raises(B.RfimError):
                 g.set_spin_storage(B.SPINS_BITS)
         g.close()
+
+
+@pytest.mark.parametrize("storage", ["bits", "bytes"])
+def test_zero_word_on_a_never_class_at_l64(rfim_mod, oracle_mod, storage):
+    """The zero word of seed 4320 (sweep 153, colour 0, replica 0,
+    sublattice index 205; the counter does not depend on L) lands at L=64 on
+    site 410 while it sits in a class whose bound is 0 at T = 0.05 (dE = 2):
+    the bit sweep and the byte sweep must both refuse it, as the oracle
+    does.  The state is compared right after sweep 153."""
+    L, seed, t, c, r, j = 64, 4320, 153, 0, 0, 205
+    i = 2 * j                                   # the colour-0 site of the pair (x + y + z even)
+    assert ((i % L) + (i // L) % L + i // (L * L)) % 2 == c
+    f = W.bimodal_fields(L, [7, L, 0])
+    T = np.array([0.05, 0.06, 0.07, 0.08])
+    o = oracle_mod.Oracle(L, 4, 1.0, 1.0, f, T, seed=seed)
+    o.sweep(t, 10)
+    w = oracle_mod.philox4x32_10([j >> 2, 2 * t + c, r, 2 << 28], [seed & 0xFFFFFFFF, seed >> 32])
+    assert w[j & 3] == 0
+    assert o.flip_delta(r, i) > 0 and not o.accept(r, i, 0)
+    o.sweep(1, 10)
+    g = rfim_mod.Rfim(L, 4, 1.0, 1.0, f, T, seed=seed)
+    if storage == "bytes":
+        g.set_spin_storage(rfim_mod.rfim.SPINS_BYTES)
+    assert g.spin_storage() == (rfim_mod.rfim.SPINS_BITS if storage == "bits" else rfim_mod.rfim.SPINS_BYTES)
+    g.sweep(t + 1, 10)
+    assert_same_state(g, o, "L=64 zero word, %s" % storage)
+    g.close()
+    o.close()
