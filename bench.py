@@ -273,29 +273,38 @@ def cpu_all_cores(procs, lib_path):
             "sample": "%d processes x (L=64, R=128, 20 sweeps, exchange every 10), %.1f s wall" % (procs, wall)}
 
 
-def hbm_streaming_leg(torch, P, W, every=10, sweeps=200, reps=5):
-    """The dominant kernel on data that does not fit the on-package cache:
-    16 realizations x R=128 at L=64 (512 MiB of spins) in one batch, so each
-    half-sweep launch covers 2048 replicas and streams them through HBM."""
+def hbm_streaming_leg(torch, P, W, every=10, sweeps=200, reps=5, blocked=True):
+    """The byte sweep on data that does not fit the on-package cache: 16
+    realizations x R=128 at L=64 (512 MiB of spins) in one batch.  With the
+    batch's temporal blocking off, each half-sweep launch covers 2048
+    replicas and streams them through HBM (the HBM-roofline figure); with
+    it on (the default of batches), groups of items run whole exchange
+    intervals inside the on-package cache."""
     specs = W.hbm_streaming_l64(sweeps=sweeps)
     stream = torch.cuda.Stream()
-    b = P.Batch(specs, stream=stream)
-    # graph capture and the first pass over the 512 MiB outside the timed
-    # region (a single warm-up interval left the first timed pass ~13 %
-    # slow); median of `reps` timed passes
-    b.sweep(5 * every, every)
-    b.synchronize()
-    times = []
-    for _ in range(reps):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        b.sweep(sweeps, every)
-        e1.record(stream)
+
+    def run(group_bytes):
+        b = P.Batch(specs, stream=stream)
+        if group_bytes is not None:
+            b.set_group_bytes(group_bytes)
+        # graph capture and the first pass over the 512 MiB outside the
+        # timed region (a single warm-up interval left the first timed pass
+        # ~13 % slow); median of `reps` timed passes
+        b.sweep(5 * every, every)
         b.synchronize()
-        times.append(e0.elapsed_time(e1) / 1e3)
-    dt = float(np.median(times))
-    b.close()
+        times = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            b.sweep(sweeps, every)
+            e1.record(stream)
+            b.synchronize()
+            times.append(e0.elapsed_time(e1) / 1e3)
+        b.close()
+        return float(np.median(times))
+
+    dt = run(0)
     attempts = sum(w.R * w.L ** 3 for w in specs) * sweeps
     spins_bytes = sum(w.R * w.L ** 3 for w in specs)
     rate = attempts / dt / 1e9
@@ -303,10 +312,15 @@ def hbm_streaming_leg(torch, P, W, every=10, sweeps=200, reps=5):
     log("hbm streaming: %d x L=64 R=%d (%.0f MiB of spins), %d sweeps: %.1f attempts/ns, %.0f GB/s "
         "algorithmic (%.1f%% of HBM)" % (len(specs), specs[0].R, spins_bytes / 2 ** 20, sweeps, rate, gbs,
                                           100 * gbs / HBM_PEAK_GBS))
-    return {"workload": "hbm_streaming_l64", "realizations": len(specs), "L": 64, "R": specs[0].R,
-            "spins_mib": round(spins_bytes / 2 ** 20, 1), "sweeps": sweeps, "exchange_every": every, "reps": reps,
-            "attempts_per_ns": round(rate, 1), "hbm_gbs_algorithmic": round(gbs, 1),
-            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    out = {"workload": "hbm_streaming_l64", "realizations": len(specs), "L": 64, "R": specs[0].R,
+           "spins_mib": round(spins_bytes / 2 ** 20, 1), "sweeps": sweeps, "exchange_every": every, "reps": reps,
+           "attempts_per_ns": round(rate, 1), "hbm_gbs_algorithmic": round(gbs, 1),
+           "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    if blocked:
+        dtb = run(None)
+        out["temporal_blocking"] = {"group_mib": 96, "attempts_per_ns": round(attempts / dtb / 1e9, 1)}
+        log("hbm streaming with temporal blocking (groups of <= 96 MiB): %.1f attempts/ns" % (attempts / dtb / 1e9))
+    return out
 
 
 def batched_leg(torch, P, W, n=256, sweeps=5000, every=10):
@@ -610,7 +624,7 @@ def main():
         copy_only(torch, args.copy_bytes)
         return
     if args.mode == "streaming":
-        hbm_streaming_leg(torch, P, W, sweeps=20, reps=1)
+        hbm_streaming_leg(torch, P, W, sweeps=20, reps=1, blocked=False)
         return
     if args.workload == "served_stream":
         served = served_leg(torch, P, W)

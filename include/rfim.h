@@ -337,6 +337,19 @@ rfim_t *rfim_batch_item(rfim_batch_t *b, int i);
 /* Launch shape of the class (L, field_kind) (see rfim_set_launch_shape);
  * used by the autotuner.  No effect on results. */
 int rfim_batch_set_shape(rfim_batch_t *b, int L, int field_kind, int mode, int nw, int wg);
+/* Temporal blocking of large streaming classes (an optimisation of the
+ * realization-level parallelism of Sec. 8; no effect on results).  A
+ * streaming class holding more than 2 * bytes of spins runs as two lanes on
+ * two streams, each a sequence of groups of consecutive items with at most
+ * `bytes` of spins (at least one item each), and a group runs all sweeps of
+ * an exchange interval before the next group of its lane, so that the
+ * groups in flight stay in the on-package cache instead of the whole class
+ * streaming through HBM once per half-sweep.  Default 96 MiB (two groups
+ * in flight within the 256 MB cache); 0 turns it off (one or two lanes
+ * over the whole class, every half-sweep over all its items).  RFIM_EINVAL
+ * for 0 < bytes < 1 MiB.  Synchronizes.  Pools (below) use the default. */
+int rfim_batch_set_group_bytes(rfim_batch_t *b, int64_t bytes);
+int64_t rfim_batch_get_group_bytes(const rfim_batch_t *b);
 
 /* ---- pools: continuous batching for serving ------------------------- */
 

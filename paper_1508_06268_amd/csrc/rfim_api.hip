@@ -1470,6 +1470,7 @@ struct rfim_batch {
         int nblocks = 0;
     };
     std::vector<Class> classes;
+    int64_t group_bytes = 96ll << 20;   // temporal blocking of large streaming classes (0: off)
     uint64_t t = 0, k = 0;
     hipGraphExec_t graph = nullptr;
     int graph_every = 0;
@@ -1569,7 +1570,7 @@ rfim_dev::Launch class_launch(const rfim_batch *b, const rfim_batch::Class &c) {
 constexpr int kMaxSideStreams = 3;
 
 struct Lane {
-    rfim_dev::Launch ln;
+    std::vector<rfim_dev::Launch> ln;   // one launch, or the groups of a large class in order
     long long work;
     bool fused;         // the class's sweep kernels write the energy partials
 };
@@ -1599,25 +1600,86 @@ int ensure_side_streams(rfim_batch *b, int n) {
     return RFIM_OK;
 }
 
+// Temporal blocking of large streaming classes.  A class whose spins exceed
+// 2 kGroupBytes runs as two lanes (the two halves of its members, on two
+// streams), and a lane as groups of consecutive members of at most
+// kGroupBytes of spins (at least one member each): a group runs all sweeps
+// of the interval before the next group of its lane starts, so the two
+// groups in flight stay inside the 256 MB on-package cache across the
+// interval's half-sweeps instead of the whole class streaming through HBM
+// once per half-sweep.  kGroupBytes is rfim_batch::group_bytes
+// (rfim_batch_set_group_bytes); 0 turns the blocking off.
+
+// The lanes of one class (see above and the two-lane split).
+void class_lanes(const rfim_batch *b, const rfim_batch::Class &c, std::vector<Lane> &lanes) {
+    const rfim_dev::Launch ln = class_launch(b, c);
+    const bool fused = class_fused(b, c);
+    const long long sites = (long long)ln.nblocks * (c.mode == 1 ? (long long)c.L * c.L * c.L / 2
+                                                                  : 4ll * c.nw * c.wg);
+    if (c.mode != 0) {
+        lanes.push_back({{ln}, sites, fused});
+        return;
+    }
+    long long bytes = 0;
+    for (int i : c.members) bytes += (long long)b->items[i]->R * b->items[i]->N;
+    const long long kGroupBytes = b->group_bytes;
+    if (kGroupBytes > 0 && bytes > 2 * kGroupBytes && c.members.size() > 1) {
+        const int wpr = rfim_dev::stream_blocks_per_replica(c.L, c.nw, c.wg);
+        const long long sites_per_block = 4ll * c.nw * c.wg;
+        // groups of consecutive members
+        std::vector<rfim_dev::Launch> groups;
+        std::vector<long long> gb;
+        int first = 0, nblk = 0;
+        long long gbytes = 0;
+        for (size_t q = 0; q <= c.members.size(); ++q) {
+            const rfim *h = q < c.members.size() ? b->items[c.members[q]] : nullptr;
+            const long long hb = h ? (long long)h->R * h->N : 0;
+            if (nblk > 0 && (!h || gbytes + hb > kGroupBytes)) {
+                rfim_dev::Launch lg = ln;
+                lg.map = ln.map + first;
+                lg.nblocks = nblk;
+                groups.push_back(lg);
+                gb.push_back(gbytes);
+                first += nblk;
+                nblk = 0;
+                gbytes = 0;
+            }
+            if (h) {
+                nblk += h->R * wpr;
+                gbytes += hb;
+            }
+        }
+        // two lanes: the groups up to half of the bytes, and the rest
+        size_t cut = 0;
+        long long acc = 0;
+        while (cut + 1 < groups.size() && 2 * (acc + gb[cut]) <= bytes) acc += gb[cut++];
+        if (cut == 0) cut = 1;
+        for (int side = 0; side < 2; ++side) {
+            Lane l{{}, 0, fused};
+            for (size_t g = side ? cut : 0; g < (side ? groups.size() : cut); ++g) {
+                l.ln.push_back(groups[g]);
+                l.work += (long long)groups[g].nblocks * sites_per_block;
+            }
+            if (!l.ln.empty()) lanes.push_back(l);
+        }
+        return;
+    }
+    if (ln.nblocks >= 16 && sites / 2 >= kSplitMinAttempts) {
+        rfim_dev::Launch la = ln, lb = ln;
+        la.nblocks = (ln.nblocks / 2) & ~7;
+        lb.map = ln.map + la.nblocks;
+        lb.nblocks = ln.nblocks - la.nblocks;
+        lanes.push_back({{la}, sites / 2, fused});
+        lanes.push_back({{lb}, sites / 2, fused});
+    } else {
+        lanes.push_back({{ln}, sites, fused});
+    }
+}
+
 // m sweeps of every item; exch: energies (fused) and one exchange step.
 int batch_segment(rfim_batch *b, int m, bool exch) {
     std::vector<Lane> lanes;
-    for (const auto &c : b->classes) {
-        const rfim_dev::Launch ln = class_launch(b, c);
-        const bool fused = class_fused(b, c);
-        const long long sites = (long long)ln.nblocks * (c.mode == 1 ? (long long)c.L * c.L * c.L / 2
-                                                                      : 4ll * c.nw * c.wg);
-        if (c.mode == 0 && ln.nblocks >= 16 && sites / 2 >= kSplitMinAttempts) {
-            rfim_dev::Launch la = ln, lb = ln;
-            la.nblocks = (ln.nblocks / 2) & ~7;
-            lb.map = ln.map + la.nblocks;
-            lb.nblocks = ln.nblocks - la.nblocks;
-            lanes.push_back({la, sites / 2, fused});
-            lanes.push_back({lb, sites / 2, fused});
-        } else {
-            lanes.push_back({ln, sites, fused});
-        }
-    }
+    for (const auto &c : b->classes) class_lanes(b, c, lanes);
     std::stable_sort(lanes.begin(), lanes.end(), [](const Lane &x, const Lane &y) { return x.work > y.work; });
     const int nside = std::min((int)lanes.size() - 1, kMaxSideStreams);
     std::vector<hipStream_t> qs(1, b->stream);
@@ -1632,15 +1694,18 @@ int batch_segment(rfim_batch *b, int m, bool exch) {
     }
     const int nq = (int)qs.size();
     for (size_t i = 0; i < lanes.size(); ++i)
-        if (lanes[i].ln.mode == 1)
-            HIPCHK(rfim_dev::launch_resident(lanes[i].ln, m, exch ? 1 : 0, qs[i % nq]));
-    for (int q = 0; q < m; ++q)
-        for (size_t i = 0; i < lanes.size(); ++i)
-            if (lanes[i].ln.mode == 0) {
-                const int e = exch && q == m - 1 && lanes[i].fused;
-                HIPCHK(rfim_dev::launch_stream_sweep(lanes[i].ln, 0, q, 0, qs[i % nq]));
-                HIPCHK(rfim_dev::launch_stream_sweep(lanes[i].ln, 1, q, e, qs[i % nq]));
-            }
+        if (lanes[i].ln[0].mode == 1)
+            HIPCHK(rfim_dev::launch_resident(lanes[i].ln[0], m, exch ? 1 : 0, qs[i % nq]));
+    // lane by lane, and in a lane group by group: a group's half-sweeps
+    // follow one another on its stream
+    for (size_t i = 0; i < lanes.size(); ++i)
+        if (lanes[i].ln[0].mode == 0)
+            for (const rfim_dev::Launch &lg : lanes[i].ln)
+                for (int q = 0; q < m; ++q) {
+                    const int e = exch && q == m - 1 && lanes[i].fused;
+                    HIPCHK(rfim_dev::launch_stream_sweep(lg, 0, q, 0, qs[i % nq]));
+                    HIPCHK(rfim_dev::launch_stream_sweep(lg, 1, q, e, qs[i % nq]));
+                }
     for (int j = 0; j < nside; ++j) {
         HIPCHK(hipEventRecord(b->ev_join[j], b->aux[j]));
         HIPCHK(hipStreamWaitEvent(b->stream, b->ev_join[j], 0));
@@ -1676,16 +1741,14 @@ constexpr long long kEagerAttemptsPerLaunch = 1ll << 26;
 
 bool batch_prefers_graph(const rfim_batch *b, int every) {
     long long attempts = 0, launches = 1;       // the exchange step
+    std::vector<Lane> lanes;
     for (const auto &c : b->classes) {
         long long per_sweep = 0;
         for (int i : c.members) per_sweep += (long long)b->items[i]->R * b->items[i]->N;
         attempts += per_sweep * every;
-        if (c.mode == 1) {
-            launches += 1;
-        } else {
-            const bool split = c.nblocks >= 16 && per_sweep / 4 >= kSplitMinAttempts;
-            launches += 2ll * every * (split ? 2 : 1);
-        }
+        lanes.clear();
+        class_lanes(b, c, lanes);
+        for (const Lane &l : lanes) launches += c.mode == 1 ? 1 : 2ll * every * (long long)l.ln.size();
     }
     return attempts < kEagerAttemptsPerLaunch * launches;
 }
@@ -1846,6 +1909,24 @@ int rfim_batch_set_shape(rfim_batch_t *b, int L, int field_kind, int mode, int n
         }
     }
     return batch_build(b);
+}
+
+int rfim_batch_set_group_bytes(rfim_batch_t *b, int64_t bytes) {
+    if (!b) return fail(RFIM_EINVAL, "batch is NULL");
+    if (bytes != 0 && bytes < (1ll << 20)) return fail(RFIM_EINVAL, "group budget must be 0 or at least 1 MiB");
+    HIPCHK(hipStreamSynchronize(b->stream));
+    b->group_bytes = bytes;
+    if (b->graph) {                 // the lanes change: capture again
+        HIPCHK(hipGraphExecDestroy(b->graph));
+        b->graph = nullptr;
+        b->graph_every = 0;
+    }
+    return RFIM_OK;
+}
+
+int64_t rfim_batch_get_group_bytes(const rfim_batch_t *b) {
+    if (!b) return fail(RFIM_EINVAL, "batch is NULL");
+    return b->group_bytes;
 }
 
 int rfim_batch_sweep(rfim_batch_t *b, int64_t n, int exchange_every) {

@@ -31,7 +31,8 @@ EXPORTS = [
     "rfim_set_launch_shape", "rfim_get_launch_shape", "rfim_set_concurrency", "rfim_get_concurrency",
     "rfim_observables", "rfim_reset_observables", "rfim_set_measure", "rfim_fourier",
     "rfim_batch_create", "rfim_batch_destroy", "rfim_batch_size", "rfim_batch_sweep",
-    "rfim_batch_synchronize", "rfim_batch_item", "rfim_batch_set_shape",
+    "rfim_batch_synchronize", "rfim_batch_item", "rfim_batch_set_shape", "rfim_batch_set_group_bytes",
+    "rfim_batch_get_group_bytes",
     "rfim_pool_create", "rfim_pool_destroy", "rfim_pool_bytes_needed", "rfim_pool_admit",
     "rfim_pool_admit_job", "rfim_pool_step", "rfim_pool_poll", "rfim_pool_result",
     "rfim_pool_adapt", "rfim_pool_release", "rfim_pool_item",
@@ -162,6 +163,8 @@ def load_library(path: str = LIB_PATH):
         "rfim_batch_synchronize": (i32, [vp]),
         "rfim_batch_item": (vp, [vp, i32]),
         "rfim_batch_set_shape": (i32, [vp, i32, i32, i32, i32, i32]),
+        "rfim_batch_set_group_bytes": (i32, [vp, i64]),
+        "rfim_batch_get_group_bytes": (i64, [vp]),
         "rfim_pool_create": (vp, [sz, vp]),
         "rfim_pool_destroy": (None, [vp]),
         "rfim_pool_bytes_needed": (sz, [C.POINTER(rfim_params_t)]),
@@ -522,6 +525,14 @@ class Batch:
     def set_shape(self, L, field_kind, mode, nw, wg):
         _check(load_library().rfim_batch_set_shape(self._b, int(L), int(field_kind), int(mode),
                                                     int(nw), int(wg)))
+
+    def set_group_bytes(self, nbytes):
+        """Group budget of the temporal blocking of large streaming classes
+        (rfim_batch_set_group_bytes); 0 turns it off."""
+        _check(load_library().rfim_batch_set_group_bytes(self._b, int(nbytes)))
+
+    def group_bytes(self) -> int:
+        return _check(load_library().rfim_batch_get_group_bytes(self._b))
 
     def item(self, i) -> Rfim:
         if self._items[i] is None:

@@ -83,6 +83,8 @@ def test_null_handle_getters_and_setters_fail_cleanly(rfim_mod):
     assert lib.rfim_num_replicas(None) == -1
     assert lib.rfim_set_measure(None, 1) == -1
     assert lib.rfim_fourier(None, None) == -1
+    assert lib.rfim_batch_set_group_bytes(None, 0) == -1
+    assert lib.rfim_batch_get_group_bytes(None) == -1
     assert b"NULL" in lib.rfim_last_error()
 
 

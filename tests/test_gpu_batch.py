@@ -189,3 +189,44 @@ def test_batch_class_without_fused_energy_matches_single_runs(rfim_mod, oracle_m
         g.close()
     assert accepted > 0
     b.close()
+
+
+def test_large_streaming_class_in_groups_equals_single_runs(rfim_mod):
+    """A streaming class larger than twice the group budget runs as two lanes
+    of groups of consecutive items, each group all sweeps of an interval
+    before the next on its stream: 7 realizations of L=64, R=128 (32 MiB of
+    byte spins each) form groups of 3, 3 and 1, the lanes [3] and [3, 1].
+    Every item equals the same realization run alone, both field kinds,
+    with accepted exchanges."""
+    specs = []
+    for rho in range(7):
+        L, R = 64, 128
+        f = W.bimodal_fields(L, [33, rho]) if rho % 2 == 0 else W.gaussian_fields(L, [33, rho])
+        specs.append(W.Realization(L=L, R=R, J=1.0, h=1.0, fields=f,
+                                   temps=W.linear_temps(R, 4.0, 4.0 + 0.0002 * (R - 1)), seed=13,
+                                   realization=rho, sweeps=0, every=3))
+    b = rfim_mod.Batch(specs)
+    assert b.group_bytes() == 96 << 20
+    b.sweep(3, 3)            # graph capture or eager, whichever the batch takes
+    b.sweep(6, 3)
+    b.synchronize()
+    flat = rfim_mod.Batch(specs)
+    flat.set_group_bytes(0)  # no temporal blocking: every half-sweep over the whole class
+    flat.sweep(9, 3)
+    flat.synchronize()
+    with pytest.raises(rfim_mod.rfim.RfimError):
+        flat.set_group_bytes(1000)
+    accepted = 0
+    for q, w in enumerate(specs):
+        g = rfim_mod.Rfim(w.L, w.R, w.J, w.h, w.fields, w.temps, seed=w.seed, realization=w.realization)
+        g.sweep(9, 3)
+        it = b.item(q)
+        assert np.array_equal(it.spins(), g.spins()), q
+        assert np.array_equal(it.perm(), g.perm()), q
+        assert np.allclose(it.energies(), g.energies(), rtol=1e-12, atol=1e-9), q
+        assert np.array_equal(flat.item(q).spins(), g.spins()), q
+        accepted += int(it.exchange_stats()[1].sum())
+        g.close()
+    assert accepted > 0
+    b.close()
+    flat.close()
