@@ -178,3 +178,24 @@ def test_pool_jobs_complete_through_the_c_abi(rfim_mod, oracle_mod):
         assert lib.rfim_pool_release(pool, s) == 0
     assert lib.rfim_pool_poll(pool, None, 0) == 0
     lib.rfim_pool_destroy(pool)
+
+
+def test_pool_large_class_in_groups_equals_alone(rfim_mod):
+    """Seven L=64 continuous-field requests of R=128 (growing towards 192
+    after the trial run): the pool's L=64 class holds more than twice the
+    96 MiB group budget of byte spins and runs as lanes of item groups
+    (temporal blocking), rebuilt after every insertion.  Each result must
+    equal the same realization run alone."""
+    reqs = [_req(q, 0.0, 64, 128, "g", trial=50, prod=50) for q in range(7)]
+    eng = PoolEngine(8 << 30)
+    res = Server(eng, quantum=50, every=10).run(reqs)
+    eng.close()
+    assert res["stats"]["completed"] == len(reqs), res["outcomes"]
+    for rq in reqs:
+        out = res["outcomes"][rq.rid]
+        g = _alone(rfim_mod, rq.spec)
+        assert out.R == g.R
+        assert np.array_equal(out.perm, g.perm()), rq.rid
+        assert np.allclose(out.energies, g.energies(), rtol=1e-12, atol=1e-9), rq.rid
+        assert np.array_equal(out.magnetizations, g.magnetizations()), rq.rid
+        g.close()
