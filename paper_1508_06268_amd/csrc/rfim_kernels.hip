@@ -387,15 +387,20 @@ __device__ __forceinline__ uint32_t cont_bound(const uint8_t *tb, uint32_t e, fl
     return cvt_u32_sat(__builtin_amdgcn_exp2f(x) * 0x1p32f);
 }
 
-// Continuous fields: four sites of one Philox block (up counts U and spins
-// Wown one per byte); bit q set iff site q flips.
-__device__ __forceinline__ uint32_t continuous_acc(const uint32_t *sthr, uint32_t U, uint32_t Wown, const f32x4 hf,
-                                                   const Words &rw) {
+// Continuous fields: four sites of one Philox block, byte q of A the table
+// entry offset (up << 4) | (s << 3) of site q; bit q set iff site q flips.
+__device__ __forceinline__ uint32_t continuous_acc_at(const uint32_t *sthr, uint32_t A, const f32x4 hf,
+                                                      const Words &rw) {
     const uint8_t *tb = (const uint8_t *)sthr;
-    const uint32_t A = (U << 4) | (Wown << 3);      // byte q: entry offset of site q
     const uint32_t b0 = cont_bound(tb, A & 0xFFu, hf.x), b1 = cont_bound(tb, (A >> 8) & 0xFFu, hf.y);
     const uint32_t b2 = cont_bound(tb, (A >> 16) & 0xFFu, hf.z), b3 = cont_bound(tb, A >> 24, hf.w);
     return accept_bits(rw.w0, rw.w1, rw.w2, rw.w3, b0, b1, b2, b3);
+}
+
+// The same from up counts U and spins Wown one per byte.
+__device__ __forceinline__ uint32_t continuous_acc(const uint32_t *sthr, uint32_t U, uint32_t Wown, const f32x4 hf,
+                                                   const Words &rw) {
+    return continuous_acc_at(sthr, (U << 4) | (Wown << 3), hf, rw);
 }
 
 // Continuous fields: four sites of one Philox block, the flips one bit
@@ -1023,6 +1028,36 @@ __device__ __forceinline__ uint32_t nibble_to_bytes(uint32_t a) {
 // position of sublattice index i (0..31) within its word
 __host__ __device__ constexpr uint32_t bit_of_index(uint32_t i) { return 8u * (i & 3u) + (i >> 2); }
 
+// Exchange the bits of a at positions i + sh with the bits of b at
+// positions i, for the positions i that mask m selects.
+__device__ __forceinline__ void swap_bit_groups(uint32_t &a, uint32_t &b, uint32_t sh, uint32_t m) {
+    const uint32_t t = ((a >> sh) ^ b) & m;
+    b ^= t;
+    a ^= t << sh;
+}
+
+// Table offsets of all eight Philox blocks of a word at once.  Byte q of
+// plane k holds bit b for block b; the table offset of site (b, q) wants
+// those five bits side by side, at bits 2 (f), 3 (s), 4..6 (up count).  With
+// planes 0, 1 and 7 zero that is an 8x8 bit transpose inside every byte:
+// three rounds of swapping bit groups of 4, 2 and 1 between planes, after
+// which plane b is byte-per-site offset word A[b] = (U << 4) | (S << 3) | (F << 2)
+// of block b.
+__device__ __forceinline__ void class_offsets(uint32_t u0, uint32_t u1, uint32_t u2, uint32_t s, uint32_t f,
+                                              uint32_t (&A)[8]) {
+    uint32_t x[8] = {0u, 0u, f, s, u0, u1, u2, 0u};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) swap_bit_groups(x[k], x[k + 4], 4u, 0x0F0F0F0Fu);
+    swap_bit_groups(x[0], x[2], 2u, 0x33333333u);
+    swap_bit_groups(x[1], x[3], 2u, 0x33333333u);
+    swap_bit_groups(x[4], x[6], 2u, 0x33333333u);
+    swap_bit_groups(x[5], x[7], 2u, 0x33333333u);
+#pragma unroll
+    for (int k = 0; k < 8; k += 2) swap_bit_groups(x[k], x[k + 1], 1u, 0x55555555u);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) A[b] = x[b];
+}
+
 constexpr int kBitsThreads = 256;
 
 __host__ __device__ constexpr int bits_wg(int L) { return L == 64 ? 128 : 256; }
@@ -1091,15 +1126,15 @@ __global__ __launch_bounds__(kBitsThreads) void sweep_bits(Lattice lat, int colo
     const uint32_t U1 = xor3(c1, c2, c3), U2 = maj3(c1, c2, c3);
     const uint32_t c1w = 2u * t + c, c3w = (kTagSweep << 28) | lat.rho;
     const uint8_t *tb = (const uint8_t *)sthr;
+    uint32_t Acls[8];
+    class_offsets(U0, U1, U2, S, KIND == 0 ? F : 0u, Acls);
     uint32_t flips = 0;
 #pragma unroll
     for (uint32_t b = 0; b < 8; ++b) {
         const Words rw = philox10(8u * w + b, c1w, r, c3w, lat.key0, lat.key1);
-        const uint32_t Ub = block_bits(U0, b) | (block_bits(U1, b) << 1) | (block_bits(U2, b) << 2);
-        const uint32_t Sb = block_bits(S, b);
         uint32_t acc;
         if (KIND == 0) {
-            const uint32_t A = (Ub << 4) | (Sb << 3) | (block_bits(F, b) << 2);
+            const uint32_t A = Acls[b];
             const uint32_t a0 = A & 0xFFu, a1 = (A >> 8) & 0xFFu, a2 = (A >> 16) & 0xFFu, a3 = A >> 24;
             const uint32_t th0 = *(const uint32_t *)(tb + a0), th1 = *(const uint32_t *)(tb + a1);
             const uint32_t th2 = *(const uint32_t *)(tb + a2), th3 = *(const uint32_t *)(tb + a3);
@@ -1116,7 +1151,7 @@ __global__ __launch_bounds__(kBitsThreads) void sweep_bits(Lattice lat, int colo
                 }
             }
         } else {
-            acc = continuous_acc(sthr, Ub, Sb, HF[b], rw);
+            acc = continuous_acc_at(sthr, Acls[b], HF[b], rw);
         }
         flips |= nibble_to_bytes(acc) << b;
     }
