@@ -43,17 +43,27 @@ template <class U> struct rebind_ptr<GAS const float *, U> { using type = GAS co
 // sequence.  Written from the published definition.
 struct Words { uint32_t w0, w1, w2, w3; };
 
-__device__ __forceinline__ Words philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                          uint32_t k0, uint32_t k1) {
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+
+// Philox4x32-10 with the first round's product M0 * c0 given: a caller
+// whose counters step by a constant can form it with one multiply-add.
+__device__ __forceinline__ Words philox10_p(uint64_t a0, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                            uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint64_t a = (uint64_t)0xD2511F53u * c0;
+        const uint64_t a = round == 0 ? a0 : (uint64_t)kPhiloxM0 * c0;
         const uint64_t b = (uint64_t)0xCD9E8D57u * c2;
         uint32_t n0, n2;
         if (round < 2) {
             // the first rounds still hold wave-uniform words: leave them to
             // the scalar unit
             n0 = (uint32_t)(b >> 32) ^ (c1 ^ k0);
+            n2 = (uint32_t)(a >> 32) ^ (c3 ^ k1);
+        } else if (round == 2) {
+            // with a wave-uniform c0 and c2 at round 0 (one site block per
+            // lane), c3 is still uniform here: one scalar XOR, one VALU XOR
+            // (a three-input VALU XOR can read only one scalar operand)
+            n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(b >> 32), c1, k0, 0x96);
             n2 = (uint32_t)(a >> 32) ^ (c3 ^ k1);
         } else {
             // three-input XOR in one VALU instruction (truth table 0x96)
@@ -68,6 +78,22 @@ __device__ __forceinline__ Words philox10(uint32_t c0, uint32_t c1, uint32_t c2,
         k1 += 0xBB67AE85u;
     }
     return Words{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ Words philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                          uint32_t k0, uint32_t k1) {
+    return philox10_p((uint64_t)kPhiloxM0 * c0, c0, c1, c2, c3, k0, k1);
+}
+
+// M0 x + c in one v_mad_u64_u32 (c a wave-uniform 64-bit addend; M0 from
+// a VGPR, since one instruction reads one scalar operand).  Written out
+// because the compiler folds M0 x + M0 b back into M0 (x + b), which costs
+// the addition of b on top of the product.  The carry-out register is not
+// read.
+__device__ __forceinline__ uint64_t mad_m0(uint32_t x, uint32_t m0, uint64_t c) {
+    uint64_t r, carry;
+    asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "=s"(carry) : "v"(x), "v"(m0), "s"(c));
+    return r;
 }
 
 __device__ __forceinline__ uint32_t word_at(const Words &w, int q) {
@@ -392,7 +418,7 @@ __device__ __forceinline__ uint32_t cont_bound(const uint8_t *tb, uint32_t e, fl
 __device__ __forceinline__ uint32_t continuous_acc_at(const uint32_t *sthr, uint32_t A, const f32x4 hf,
                                                       const Words &rw) {
     const uint8_t *tb = (const uint8_t *)sthr;
-    const uint32_t b0 = cont_bound(tb, A & 0xFFu, hf.x), b1 = cont_bound(tb, (A >> 8) & 0xFFu, hf.y);
+    const uint32_t b0 = cont_bound(tb, A & 0xFFu, hf.x), b1 = cont_bound(tb, __builtin_amdgcn_ubfe(A, 8u, 8u), hf.y);
     const uint32_t b2 = cont_bound(tb, (A >> 16) & 0xFFu, hf.z), b3 = cont_bound(tb, A >> 24, hf.w);
     return accept_bits(rw.w0, rw.w1, rw.w2, rw.w3, b0, b1, b2, b3);
 }
@@ -1128,14 +1154,18 @@ __global__ __launch_bounds__(kBitsThreads) void sweep_bits(Lattice lat, int colo
     const uint8_t *tb = (const uint8_t *)sthr;
     uint32_t Acls[8];
     class_offsets(U0, U1, U2, S, KIND == 0 ? F : 0u, Acls);
+    const uint32_t m0v = __builtin_amdgcn_readfirstlane(kPhiloxM0);   // held in one VGPR below
     uint32_t flips = 0;
 #pragma unroll
     for (uint32_t b = 0; b < 8; ++b) {
-        const Words rw = philox10(8u * w + b, c1w, r, c3w, lat.key0, lat.key1);
+        // block counters 8w + b: the first product M0 (8w + b) is one
+        // multiply-add of 8w with the constant M0 b
+        const Words rw = philox10_p(mad_m0(8u * w, m0v, (uint64_t)kPhiloxM0 * b), 8u * w + b, c1w, r, c3w,
+                                    lat.key0, lat.key1);
         uint32_t acc;
         if (KIND == 0) {
             const uint32_t A = Acls[b];
-            const uint32_t a0 = A & 0xFFu, a1 = (A >> 8) & 0xFFu, a2 = (A >> 16) & 0xFFu, a3 = A >> 24;
+            const uint32_t a0 = A & 0xFFu, a1 = __builtin_amdgcn_ubfe(A, 8u, 8u), a2 = (A >> 16) & 0xFFu, a3 = A >> 24;
             const uint32_t th0 = *(const uint32_t *)(tb + a0), th1 = *(const uint32_t *)(tb + a1);
             const uint32_t th2 = *(const uint32_t *)(tb + a2), th3 = *(const uint32_t *)(tb + a3);
             acc = accept_bits(rw.w0, rw.w1, rw.w2, rw.w3, th0, th1, th2, th3);
