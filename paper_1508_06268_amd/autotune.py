@@ -3,9 +3,10 @@
 Every launch shape gives bit-identical chains, so the tuner only measures
 time.  For each class (L, field kind) of a batch it times a probe batch built
 from the same realization specs (so the real chains are not advanced) over a
-few exchange intervals per candidate shape, one class at a time with the
-others fixed, and keeps the fastest.  Results are cached in a JSON file keyed
-by (L, field kind, replicas of the class, members of the class).
+few exchange intervals per candidate shape, each class alone, then refines the
+choice on the whole batch (the classes run concurrently, and a shape that is
+fastest alone can lose beside the others).  Results are cached in a JSON file
+keyed by (L, field kind, replicas of the class, members of the class).
 
 The paper picks its block by minimising the halo surface of a w x x x y box
 of fixed volume V (Sec. 3.2, Eq. 4-5): x = y = sqrt(V/w), giving
@@ -71,7 +72,7 @@ def _kind_of(w) -> int:
 
 # Bumped whenever the kernels or the timing method change, so that shapes
 # cached by an older build are measured again.
-CACHE_VERSION = 2
+CACHE_VERSION = 3
 
 
 def class_key(L: int, kind: int, items) -> str:
@@ -110,8 +111,16 @@ def _time_batch(torch, batch, stream, every: int, intervals: int) -> float:
 
 
 def tune(specs, every: int = 10, intervals: int = 3, cache_path: Optional[str] = DEFAULT_CACHE,
-         log=None) -> Dict[Tuple[int, int], Tuple[int, int, int]]:
-    """Best shape per (L, field kind) class of the given realization specs."""
+         log=None, refine_top: int = 3) -> Dict[Tuple[int, int], Tuple[int, int, int]]:
+    """Best shape per (L, field kind) class of the given realization specs.
+
+    Two stages.  Each class alone: every candidate shape on a probe batch of
+    that class's specs, best of two passes.  Then the whole batch, because
+    the classes of a batch run concurrently on their lanes and a shape that
+    wins alone can lose beside the others (a streaming shape's many short
+    launches against the other lanes' work): class by class, largest first,
+    its `refine_top` fastest shapes alone are timed in the full batch with
+    the other classes fixed, and the fastest there is kept."""
     import torch
 
     classes: Dict[Tuple[int, int], list] = {}
@@ -128,10 +137,8 @@ def tune(specs, every: int = 10, intervals: int = 3, cache_path: Optional[str] =
             todo.append(key)
     if todo:
         stream = torch.cuda.Stream()
+        alone: Dict[Tuple[int, int], Dict[Tuple[int, int, int], float]] = {}
         for key in todo:
-            # each class is timed on its own (the classes of a batch run
-            # concurrently, so a whole-batch time would mix them), best of
-            # two passes over the candidates
             L, kind = key
             probe = Batch(classes[key], stream=stream)
             timings = {}
@@ -143,9 +150,36 @@ def tune(specs, every: int = 10, intervals: int = 3, cache_path: Optional[str] =
                     if log:
                         log("tune L=%d kind=%d shape %s: %.3f ms" % (L, kind, shape, ms))
             probe.close()
-            shape = min(timings, key=lambda sh: (timings[sh], sh))
-            best[key] = shape
-            cache[class_key(L, kind, classes[key])] = list(shape)
+            alone[key] = timings
+            best[key] = min(timings, key=lambda sh: (timings[sh], sh))
+        if refine_top > 1 and len(classes) > 1:
+            full = Batch(specs, stream=stream)
+            apply(full, best)
+
+            def whole():
+                return min(_time_batch(torch, full, stream, every, intervals) for _ in range(2))
+
+            base = whole()
+            work = {k: sum(int(w.R) * int(w.L) ** 3 for w in classes[k]) for k in todo}
+            for key in sorted(todo, key=lambda k: -work[k]):
+                L, kind = key
+                cands = sorted(alone[key], key=lambda sh: (alone[key][sh], sh))[:refine_top]
+                for shape in cands:
+                    if shape == best[key]:
+                        continue
+                    full.set_shape(L, kind, *shape)
+                    ms = whole()
+                    if log:
+                        log("tune whole batch, L=%d kind=%d shape %s: %.3f ms (best %.3f)" % (L, kind, shape, ms,
+                                                                                           base))
+                    if ms < base:
+                        base = ms
+                        best[key] = shape
+                    else:
+                        full.set_shape(L, kind, *best[key])
+            full.close()
+        for key in todo:
+            cache[class_key(key[0], key[1], classes[key])] = list(best[key])
         if cache_path:
             save_cache(cache, cache_path)
     return best
