@@ -1030,9 +1030,11 @@ __global__ __launch_bounds__(1024) void sweep_tiles(Lattice lat, TileShape ts, i
 // shifted by one index along the row with the neighbouring word's end bit
 // (index m-1 when (c+y+z) is even, m+1 when odd, as in the byte layout),
 // and the words of rows y+-1 and z+-1.  A bit-sliced full-adder tree turns
-// the six into three planes of the up count; per Philox block a shift and
-// a mask per plane give the byte-per-site operands of the byte sweep's
-// decision, which runs on the same random words, so the chain is the same.
+// the six into three planes of the up count; a bit transpose of the class
+// planes gives every Philox block's byte-per-site table offsets, the
+// operands of the byte sweep's decision, which runs on the same random
+// words, so the chain is the same.  (Two words per thread, tried, ran the
+// two-stream half-sweep 8 % slower: fewer waves to hide latency.)
 // ---------------------------------------------------------------------
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
@@ -1041,8 +1043,6 @@ __device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);
 }
 constexpr uint32_t kByteLsb = 0x01010101u;
-// bit b of each byte of v, to bit 0
-__device__ __forceinline__ uint32_t block_bits(uint32_t v, uint32_t b) { return (v >> b) & kByteLsb; }
 // bits 0..3 of a to bit 0 of bytes 0..3: a 24-bit multiply written out, so
 // that a later shift is not folded into a constant the 24-bit form cannot
 // take
