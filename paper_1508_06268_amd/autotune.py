@@ -111,7 +111,7 @@ def _time_batch(torch, batch, stream, every: int, intervals: int) -> float:
 
 
 def tune(specs, every: int = 10, intervals: int = 3, cache_path: Optional[str] = DEFAULT_CACHE,
-         log=None, refine_top: int = 3) -> Dict[Tuple[int, int], Tuple[int, int, int]]:
+         log=None, refine_top: int = 3, whole_intervals: int = 10) -> Dict[Tuple[int, int], Tuple[int, int, int]]:
     """Best shape per (L, field kind) class of the given realization specs.
 
     Two stages.  Each class alone: every candidate shape on a probe batch of
@@ -120,7 +120,9 @@ def tune(specs, every: int = 10, intervals: int = 3, cache_path: Optional[str] =
     wins alone can lose beside the others (a streaming shape's many short
     launches against the other lanes' work): class by class, largest first,
     its `refine_top` fastest shapes alone are timed in the full batch with
-    the other classes fixed, and the fastest there is kept."""
+    the other classes fixed (over `whole_intervals` exchange intervals,
+    starting from the better of the batch's default shapes and the shapes
+    fastest alone), and the fastest there is kept."""
     import torch
 
     classes: Dict[Tuple[int, int], list] = {}
@@ -154,12 +156,26 @@ def tune(specs, every: int = 10, intervals: int = 3, cache_path: Optional[str] =
             best[key] = min(timings, key=lambda sh: (timings[sh], sh))
         if refine_top > 1 and len(classes) > 1:
             full = Batch(specs, stream=stream)
-            apply(full, best)
+            first = {}
+            for q, w in enumerate(specs):
+                first.setdefault((int(w.L), _kind_of(w)), tuple(full.item(q).launch_shape()))
 
             def whole():
-                return min(_time_batch(torch, full, stream, every, intervals) for _ in range(2))
+                return min(_time_batch(torch, full, stream, every, whole_intervals) for _ in range(2))
 
+            # start from the better of the batch's default shapes and the
+            # shapes that won alone (a class-by-class search from the latter
+            # can miss a combination the defaults already hold)
+            t_default = whole()
+            apply(full, best)
             base = whole()
+            if log:
+                log("tune whole batch: default shapes %.3f ms, shapes fastest alone %.3f ms" % (t_default, base))
+            if t_default < base:
+                for key in todo:
+                    best[key] = first[key]
+                apply(full, best)
+                base = t_default
             work = {k: sum(int(w.R) * int(w.L) ** 3 for w in classes[k]) for k in todo}
             for key in sorted(todo, key=lambda k: -work[k]):
                 L, kind = key
