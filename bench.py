@@ -765,12 +765,16 @@ def main():
 
     for hh in handles:
         hh.close()
+    # the realization-level legs first: a batch's concurrent lanes and a
+    # pool's ran slower in a process that had already run the HBM-size legs
+    # (the hardware queues its streams land on follow from how many streams
+    # the process made before)
+    batched = None if args.no_batched else batched_leg(torch, P, W)
+    served = None if args.no_served else served_leg(torch, P, W)
     streaming = hbm_streaming_leg(torch, P, W)
     roofline["hbm_streaming"] = streaming
     roofline["hbm_size_bits"] = hbm_bits_leg(torch, P, W)
     paper_scale = paper_scale_leg(torch, P, W)
-    batched = None if args.no_batched else batched_leg(torch, P, W)
-    served = None if args.no_served else served_leg(torch, P, W)
     # last of the GPU legs: its sustained VALU load can lower the clock for
     # what follows
     multi_hit = multi_hit_leg(torch, P, W)

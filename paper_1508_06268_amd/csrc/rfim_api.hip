@@ -124,54 +124,6 @@ void release_side_stream(hipStream_t side) {
         }
 }
 
-// The lane streams of batches, from a pool per device: a batch takes
-// streams no other live batch holds and returns them when it is destroyed;
-// the streams stay for the next batch.  Each has a hardware queue of its
-// own (create_lane_stream), so the lanes of a batch never share one.  Plain
-// streams, created per batch, did: the queue a plain stream lands on
-// follows from how many streams the process made before, and the
-// 256-realization batch ran at 331-372 realizations/s instead of 480-510
-// after the other benchmark legs; created and destroyed per batch, queues
-// of their own were slow after the autotuner's many probe batches.  Pools,
-// which launch every quantum eagerly and meet their lanes by events at
-// every exchange step, ran slower on such queues (served capacity 96
-// against 113 realizations/s) and keep plain lane streams of their own.
-struct LaneStream {
-    int device;
-    hipStream_t q;
-    bool busy;
-};
-std::vector<LaneStream> g_lanes;
-
-hipError_t acquire_lane_stream(hipStream_t *q) {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    std::lock_guard<std::mutex> lock(g_side_mu);
-    for (auto &l : g_lanes)
-        if (l.device == dev && !l.busy) {
-            l.busy = true;
-            *q = l.q;
-            return hipSuccess;
-        }
-    hipStream_t n = nullptr;
-    if ((e = create_lane_stream(&n)) != hipSuccess) return e;
-    g_lanes.push_back({dev, n, true});
-    *q = n;
-    return hipSuccess;
-}
-
-// The batch has synchronized its stream, which every lane joins back into.
-void release_lane_stream(hipStream_t q) {
-    if (!q) return;
-    std::lock_guard<std::mutex> lock(g_side_mu);
-    for (auto &l : g_lanes)
-        if (l.q == q) {
-            l.busy = false;
-            return;
-        }
-}
-
 }  // namespace
 
 namespace rfim_host {
@@ -1529,10 +1481,6 @@ struct rfim_batch {
     std::vector<hipStream_t> aux;
     std::vector<hipEvent_t> ev_join;
     hipEvent_t ev_fork = nullptr;
-    // lanes on plain streams of the batch's own (pools: launched eagerly
-    // every quantum) rather than on pooled streams with hardware queues of
-    // their own (batches: captured and replayed)
-    bool plain_lanes = false;
 };
 
 namespace {
@@ -1552,12 +1500,7 @@ void batch_free(rfim_batch *b) {
     }
     if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
     for (hipEvent_t e : b->ev_join) (void)hipEventDestroy(e);
-    for (hipStream_t q : b->aux) {
-        if (b->plain_lanes)
-            (void)hipStreamDestroy(q);
-        else
-            release_lane_stream(q);
-    }
+    for (hipStream_t q : b->aux) (void)hipStreamDestroy(q);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
@@ -1646,10 +1589,10 @@ int ensure_side_streams(rfim_batch *b, int n) {
     while ((int)b->aux.size() < n) {
         hipStream_t q = nullptr;
         hipEvent_t e = nullptr;
-        if (b->plain_lanes)
-            HIPCHK(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
-        else
-            HIPCHK(acquire_lane_stream(&q));
+        // plain streams: lanes of a batch made right after many short-lived
+        // batches (the autotuner's probes) ran ~30 % slower on CU-masked
+        // queues of their own
+        HIPCHK(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
         b->aux.push_back(q);
         HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         b->ev_join.push_back(e);
@@ -2148,7 +2091,6 @@ rfim_pool_t *rfim_pool_create(size_t hbm_budget_bytes, void *hip_stream) {
         return nullptr;
     }
     p->budget = hbm_budget_bytes;
-    p->core.plain_lanes = true;
     if (hip_stream) {
         p->core.stream = (hipStream_t)hip_stream;
     } else {
@@ -2174,7 +2116,6 @@ void rfim_pool_destroy(rfim_pool_t *p) {
         b->d_lats = p->core.d_lats;
         b->classes = p->core.classes;
         b->aux = p->core.aux;
-        b->plain_lanes = p->core.plain_lanes;
         b->ev_join = p->core.ev_join;
         b->ev_fork = p->core.ev_fork;
         for (rfim *h : p->slots)
