@@ -164,11 +164,11 @@ def kernel_only(torch, P, W, sweeps, storage):
 
 def gauss_kernel_only(torch, P, W, which, sweeps=20):
     """Only a continuous-field sweep, for counters: `streaming` is L=64,
-    R=128 (Gaussian fields, h=2) on one stream, `paper_scale` the L=32,
-    R=64 shape on its default slab launch, `resident` the same on the
-    LDS-resident launch (1, 4, 1024); `sweeps` sweeps with an exchange
-    every 10."""
-    if which == "streaming":
+    R=128 (Gaussian fields, h=2) in byte storage on one stream, `bits` the
+    same in bit storage (its default), `paper_scale` the L=32, R=64 shape on
+    its default slab launch, `resident` the same on the LDS-resident launch
+    (1, 4, 1024); `sweeps` sweeps with an exchange every 10."""
+    if which in ("streaming", "bits"):
         L, R = 64, 128
     else:
         L, R = 32, 64
@@ -177,10 +177,12 @@ def gauss_kernel_only(torch, P, W, which, sweeps=20):
                stream=stream)
     if which == "resident":
         h.set_launch_shape(1, 4, 1024)
+    h.set_spin_storage(P.rfim.SPINS_BITS if which == "bits" else P.rfim.SPINS_BYTES)
     h.set_concurrency(1)
     h.sweep(sweeps, 10)
     h.synchronize()
-    log("gauss %s mode: L=%d R=%d shape %s, %d sweeps" % (which, L, R, h.launch_shape(), sweeps))
+    log("gauss %s mode: L=%d R=%d shape %s, storage %d, %d sweeps" % (which, L, R, h.launch_shape(),
+                                                                       h.spin_storage(), sweeps))
 
 
 def hbm_bits_leg(torch, P, W, n=128, R=128, sweeps=100, every=10):
@@ -562,11 +564,12 @@ def main():
     ap.add_argument("--production-sweeps", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="bench", choices=["bench", "kernel", "kernel_bits", "kernel_gauss",
-                                                     "paper_scale_gauss", "resident_gauss", "tiles",
+                                                     "bits_gauss", "paper_scale_gauss", "resident_gauss", "tiles",
                                                      "streaming", "copy"],
                     help="kernel / kernel_bits: only the byte / bit sweep kernel (for counters); kernel_gauss / "
-                         "paper_scale_gauss / resident_gauss: only the continuous-field streaming sweep (L=64, "
-                         "R=128) / the L=32, R=64 sweep on its default slab shape / on the LDS-resident shape; "
+                         "bits_gauss / paper_scale_gauss / resident_gauss: only the continuous-field streaming "
+                         "sweep (L=64, R=128) in bytes / in bits / the L=32, R=64 sweep on its default slab "
+                         "shape / on the LDS-resident shape; "
                          "tiles: only "
                          "the multi-hit "
                          "tile kernel (for counters); streaming: only the "
@@ -613,9 +616,9 @@ def main():
     if args.mode in ("kernel", "kernel_bits"):
         kernel_only(torch, P, W, 20, P.rfim.SPINS_BITS if args.mode == "kernel_bits" else P.rfim.SPINS_BYTES)
         return
-    if args.mode in ("kernel_gauss", "paper_scale_gauss", "resident_gauss"):
-        gauss_kernel_only(torch, P, W, {"kernel_gauss": "streaming", "paper_scale_gauss": "paper_scale",
-                                        "resident_gauss": "resident"}[args.mode])
+    if args.mode in ("kernel_gauss", "bits_gauss", "paper_scale_gauss", "resident_gauss"):
+        gauss_kernel_only(torch, P, W, {"kernel_gauss": "streaming", "bits_gauss": "bits",
+                                        "paper_scale_gauss": "paper_scale", "resident_gauss": "resident"}[args.mode])
         return
     if args.mode == "tiles":
         tiles_only(torch, P, W)

@@ -278,10 +278,10 @@ int rfim_get_concurrency(const rfim_t *h);
  * Bits are valid for L = 64, 128 or 256 in the plain checkerboard order
  * without the Fourier measurement (RFIM_EINVAL / RFIM_ESTATE otherwise,
  * RFIM_ENOMEM if the bit arrays, R_cap * L^3 / 8 bytes plus L^3 / 8 for
- * +-1 fields, allocated on first use, cannot be had).  A handle made by
- * rfim_create / rfim_create_ex / rfim_load with +-1 fields at L = 64..256
- * or continuous fields at L = 128, 256 starts in bits, every other handle
- * in bytes; rfim_set_launch_shape (its
+ * +-1 fields or 4 L^3 for continuous fields (a copy of the fields in the
+ * bit sweep's order), allocated on first use, cannot be had).  A handle
+ * made by rfim_create / rfim_create_ex / rfim_load at L = 64..256 starts
+ * in bits, every other handle in bytes; rfim_set_launch_shape (its
  * shapes are the byte kernels'), rfim_set_measure with the Fourier flag and
  * rfim_set_update_order with tiles switch a handle to bytes.  Calls that
  * read or write spins (energies, spins, checkpoints, adaptive insertion)

@@ -21,7 +21,7 @@ import math
 import os
 from typing import Dict, List, Optional, Tuple
 
-from .rfim import FIELDS_BIMODAL, FIELDS_CONTINUOUS, Batch
+from .rfim import FIELDS_BIMODAL, FIELDS_CONTINUOUS, MODE_BITS, Batch
 
 DEFAULT_CACHE = os.environ.get(
     "RFIM_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "rfim_mi355x_tune.json"))
@@ -40,7 +40,9 @@ def halo_surface(w: int, x: float, y: float) -> float:
 
 
 def candidate_shapes(L: int) -> List[Tuple[int, int, int]]:
-    """Valid (mode, dwords per thread, threads per workgroup) for L."""
+    """Valid (mode, dwords per thread, threads per workgroup) for L; at
+    L = 64, 128 and 256 also one bit per spin, (MODE_BITS, 0, 0), tried
+    first."""
     out = []
     for nw in (1, 2, 4, 8):
         if 4 * nw > L // 2:
@@ -57,6 +59,8 @@ def candidate_shapes(L: int) -> List[Tuple[int, int, int]]:
     _, y, x = halo_optimal_block(2 * 1024, 64)
     opt = 64 * y * x // 2
     out.sort(key=lambda s: (abs(math.log2(s[2] * 4 * s[1]) - math.log2(max(opt, 1))), s))
+    if L in (64, 128, 256):
+        out.insert(0, (MODE_BITS, 0, 0))
     return out
 
 
@@ -72,7 +76,7 @@ def _kind_of(w) -> int:
 
 # Bumped whenever the kernels or the timing method change, so that shapes
 # cached by an older build are measured again.
-CACHE_VERSION = 3
+CACHE_VERSION = 4
 
 
 def class_key(L: int, kind: int, items) -> str:

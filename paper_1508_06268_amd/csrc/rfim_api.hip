@@ -169,6 +169,7 @@ struct rfim {
     // date before any call that reads it)
     bool bits_mode = false;
     uint32_t *d_bits = nullptr, *d_fbw = nullptr;
+    float *d_fhw = nullptr;          // continuous fields in the bit sweep's order
     // slab shapes (mode >= 2) read one spin buffer and write the other;
     // d_spins is always the current one, d_spins_alt the other, and
     // d_spins_own the second buffer as allocated (freed with the handle)
@@ -236,6 +237,7 @@ struct rfim {
         a.obs = d_obs;
         a.bits = bits_mode ? d_bits : nullptr;
         a.fbw = d_fbw;
+        a.fhw = d_fhw;
         return a;
     }
 };
@@ -273,6 +275,7 @@ void free_device(rfim *h) {
     dev_free(h, h->d_fobs);
     dev_free(h, (void *)h->d_bits);
     dev_free(h, (void *)h->d_fbw);
+    dev_free(h, (void *)h->d_fhw);
     dev_free(h, (void *)h->d_spins_own);
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);
@@ -686,10 +689,11 @@ void destroy_impl(rfim *h) {
 // never interact within an exchange interval, and the two launch sequences
 // fill each other's start-up and drain time.  Worth it only for launches
 // that are large on their own: from 2^22 sites of one colour per half (R >= 64
-// at L = 64) for byte spins and continuous fields, from 2^23 for the bit sweep
-// with +-1 fields, whose launches are shortest (measured on gfx950: at L = 64,
-// R = 64 one stream runs 1196 attempts/ns against 827 split, at R = 128 the
-// split wins, 1709 against 1575).
+// at L = 64) for byte spins, from 2^23 for the bit sweep, whose launches are
+// shortest (measured on gfx950 at L = 64, +-1 fields: R = 64 one stream runs
+// 1196 attempts/ns against 827 split, at R = 128 the split wins, 1709 against
+// 1575; continuous fields: 1128 against 957 at R = 64, 1421 against 1708 at
+// R = 128).
 constexpr long long kSplitMinAttempts = 1ll << 22;
 constexpr long long kSplitMinAttemptsBits = 1ll << 23;
 
@@ -714,7 +718,7 @@ int sweep_impl(rfim *h, int64_t n, int every) {
     const bool tiled = h->order == 1;
     const bool bitsm = h->bits_mode;
     const bool big = (long long)(h->R / 2) * h->half >=
-                     (bitsm && h->kind == 0 ? kSplitMinAttemptsBits : kSplitMinAttempts);
+                     (bitsm ? kSplitMinAttemptsBits : kSplitMinAttempts);
     const bool split = !tiled && pow2 && (bitsm || h->mode == 0) && h->R >= 2 &&
                        (h->concurrency == 2 || (h->concurrency == 0 && big));
     rfim_dev::Launch la = ln, lb = ln;
@@ -857,13 +861,11 @@ rfim_t *rfim_create_ex(const rfim_params_t *params, const rfim_alloc_t *alloc, v
         g_error = msg;
         return nullptr;
     }
-    // +-1 fields at L = 64..256 and continuous fields at L = 128, 256
-    // default to one bit per spin, the faster storage there (the same
-    // chain; measured on gfx950, continuous fields: +26-44 % at L = 128,
-    // -7..+3 % at L = 64, which keeps bytes); if its arrays cannot be had
-    // the handle keeps byte spins
-    if (rfim_dev::bits_valid(h->L) && (h->kind == 0 || h->L >= 128) &&
-        rfim_set_spin_storage(h, RFIM_SPINS_BITS) != RFIM_OK) {
+    // L = 64..256 defaults to one bit per spin, the faster storage there
+    // for both field kinds (the same chain; measured on gfx950, continuous
+    // fields: +19-25 % at L = 64, +32-50 % at L = 128); if its arrays cannot
+    // be had the handle keeps byte spins
+    if (rfim_dev::bits_valid(h->L) && rfim_set_spin_storage(h, RFIM_SPINS_BITS) != RFIM_OK) {
         (void)hipGetLastError();
         g_error.clear();
     }
@@ -1278,11 +1280,11 @@ int rfim_set_update_order(rfim_t *h, int order, int tx, int ty, int tz, int hits
     return RFIM_OK;
 }
 
-int rfim_set_spin_storage(rfim_t *h, int storage) {
-    if (!h) return fail(RFIM_EINVAL, "handle is NULL");
-    if (h->in_batch) return fail(RFIM_ESTATE, "batch and pool items keep byte spins");
-    if (storage != RFIM_SPINS_BYTES && storage != RFIM_SPINS_BITS)
-        return fail(RFIM_EINVAL, "unknown spin storage %d", storage);
+namespace {
+
+// Switch a handle's spin storage (a batch or pool item's too: its class
+// shape decides); switching to bytes leaves the launch shape as it is.
+int set_storage_impl(rfim *h, int storage) {
     if (storage == (h->bits_mode ? RFIM_SPINS_BITS : RFIM_SPINS_BYTES)) return RFIM_OK;
     if (storage == RFIM_SPINS_BITS) {
         if (!rfim_dev::bits_valid(h->L))
@@ -1294,9 +1296,12 @@ int rfim_set_spin_storage(rfim_t *h, int storage) {
             const size_t words = (size_t)h->R_cap * (size_t)h->N / 32;
             int rc = dev_alloc(h, (void **)&h->d_bits, words * 4);
             if (!rc && h->kind == 0) rc = dev_alloc(h, (void **)&h->d_fbw, (size_t)h->N / 8);
+            if (!rc && h->kind == 1) rc = dev_alloc(h, (void **)&h->d_fhw, (size_t)h->N * sizeof(float));
             if (rc) {
                 dev_free(h, (void *)h->d_bits);
+                dev_free(h, (void *)h->d_fbw);
                 h->d_bits = nullptr;
+                h->d_fbw = nullptr;
                 return rc;
             }
         }
@@ -1309,6 +1314,18 @@ int rfim_set_spin_storage(rfim_t *h, int storage) {
         h->nblk = rfim_dev::blocks_per_replica(h->L, h->mode, h->nw, h->wg);
     }
     return sync_descriptor(h);
+}
+
+}  // namespace
+
+int rfim_set_spin_storage(rfim_t *h, int storage) {
+    if (!h) return fail(RFIM_EINVAL, "handle is NULL");
+    if (h->in_batch)
+        return fail(RFIM_ESTATE, "batch and pool items take their storage from the class shape "
+                                 "(rfim_batch_set_shape / rfim_pool_set_shape)");
+    if (storage != RFIM_SPINS_BYTES && storage != RFIM_SPINS_BITS)
+        return fail(RFIM_EINVAL, "unknown spin storage %d", storage);
+    return set_storage_impl(h, storage);
 }
 
 int rfim_get_spin_storage(const rfim_t *h) {
@@ -1485,6 +1502,40 @@ struct rfim_batch {
 
 namespace {
 
+// A batch or pool item to its class shape: one bit per spin for
+// (kModeBits, 0, 0), byte spins with that launch shape otherwise.
+int item_apply_shape(rfim *h, int mode, int nw, int wg) {
+    int rc;
+    if (mode == rfim_dev::kModeBits) {
+        if ((rc = set_storage_impl(h, RFIM_SPINS_BITS))) return rc;
+        h->mode = mode;
+        h->nw = 0;
+        h->wg = 0;
+        return sync_descriptor(h);
+    }
+    h->mode = mode;
+    h->nw = nw;
+    h->wg = wg;
+    if (h->bits_mode) return set_storage_impl(h, RFIM_SPINS_BYTES);   // sets nblk from the shape
+    h->nblk = rfim_dev::blocks_per_replica(h->L, mode, nw, wg);
+    return sync_descriptor(h);
+}
+
+// A class shape batches and pools take (the single-realization shapes
+// without the slabs, and the bit storage).
+int check_class_shape(int L, int mode, int nw, int wg) {
+    if (mode == rfim_dev::kModeBits) {
+        if (!rfim_dev::bits_valid(L) || nw != 0 || wg != 0)
+            return fail(RFIM_EINVAL, "bit storage (%d, 0, 0) needs L = 64, 128 or 256 (got L=%d, shape (%d, %d, %d))",
+                        rfim_dev::kModeBits, L, mode, nw, wg);
+        return RFIM_OK;
+    }
+    if (mode >= 2) return fail(RFIM_EINVAL, "slab shapes are for single realizations");
+    if (!rfim_dev::shape_valid(L, mode, nw, wg))
+        return fail(RFIM_EINVAL, "launch shape (%d, %d, %d) not valid for L=%d", mode, nw, wg, L);
+    return RFIM_OK;
+}
+
 void batch_free(rfim_batch *b) {
     if (!b) return;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
@@ -1515,6 +1566,10 @@ int batch_build(rfim_batch *b) {
     for (size_t ci = 0; ci < b->classes.size(); ++ci) {
         auto &c = b->classes[ci];
         std::vector<uint2> &map = maps[ci];
+        if (c.mode == rfim_dev::kModeBits) {    // launched item by item, no map
+            c.nblocks = 0;
+            continue;
+        }
         for (int i : c.members) {
             const rfim *h = b->items[i];
             const uint32_t hi = (uint32_t)i << 16;
@@ -1569,8 +1624,15 @@ rfim_dev::Launch class_launch(const rfim_batch *b, const rfim_batch::Class &c) {
 // to the batch stream and up to kMaxSideStreams side streams.
 constexpr int kMaxSideStreams = 3;
 
+// Replicas r0 .. r0 + nrep - 1 of batch item `item` (bit storage).
+struct BitsPart {
+    int item, r0, nrep;
+};
+
 struct Lane {
+    int mode;                           // the class's launch mode
     std::vector<rfim_dev::Launch> ln;   // one launch, or the groups of a large class in order
+    std::vector<BitsPart> parts;        // kModeBits: the items (or replica halves) in order
     long long work;
     bool fused;         // the class's sweep kernels write the energy partials
 };
@@ -1612,12 +1674,40 @@ int ensure_side_streams(rfim_batch *b, int n) {
 
 // The lanes of one class (see above and the two-lane split).
 void class_lanes(const rfim_batch *b, const rfim_batch::Class &c, std::vector<Lane> &lanes) {
+    if (c.mode == rfim_dev::kModeBits) {
+        // each item runs all sweeps of the interval before the next item of
+        // its lane starts (its bits stay in the caches); two lanes from
+        // kSplitMinAttemptsBits sites per half, as for one realization
+        long long sites = 0;
+        for (int i : c.members) sites += (long long)b->items[i]->R * b->items[i]->half;
+        if (c.members.empty()) return;
+        if (sites / 2 < kSplitMinAttemptsBits) {
+            Lane l{c.mode, {}, {}, sites, true};
+            for (int i : c.members) l.parts.push_back({i, 0, b->items[i]->R});
+            lanes.push_back(l);
+        } else if (c.members.size() == 1) {
+            const int i = c.members[0], R = b->items[i]->R, ra = R / 2;
+            lanes.push_back({c.mode, {}, {{i, 0, ra}}, (long long)ra * b->items[i]->half, true});
+            lanes.push_back({c.mode, {}, {{i, ra, R - ra}}, (long long)(R - ra) * b->items[i]->half, true});
+        } else {
+            Lane la{c.mode, {}, {}, 0, true}, lb{c.mode, {}, {}, 0, true};
+            for (int i : c.members) {
+                const long long w = (long long)b->items[i]->R * b->items[i]->half;
+                Lane &l = la.parts.empty() || 2 * (la.work + w) <= sites ? la : lb;
+                l.parts.push_back({i, 0, b->items[i]->R});
+                l.work += w;
+            }
+            lanes.push_back(la);
+            if (!lb.parts.empty()) lanes.push_back(lb);
+        }
+        return;
+    }
     const rfim_dev::Launch ln = class_launch(b, c);
     const bool fused = class_fused(b, c);
     const long long sites = (long long)ln.nblocks * (c.mode == 1 ? (long long)c.L * c.L * c.L / 2
                                                                   : 4ll * c.nw * c.wg);
     if (c.mode != 0) {
-        lanes.push_back({{ln}, sites, fused});
+        lanes.push_back({c.mode, {ln}, {}, sites, fused});
         return;
     }
     long long bytes = 0;
@@ -1655,7 +1745,7 @@ void class_lanes(const rfim_batch *b, const rfim_batch::Class &c, std::vector<La
         while (cut + 1 < groups.size() && 2 * (acc + gb[cut]) <= bytes) acc += gb[cut++];
         if (cut == 0) cut = 1;
         for (int side = 0; side < 2; ++side) {
-            Lane l{{}, 0, fused};
+            Lane l{c.mode, {}, {}, 0, fused};
             for (size_t g = side ? cut : 0; g < (side ? groups.size() : cut); ++g) {
                 l.ln.push_back(groups[g]);
                 l.work += (long long)groups[g].nblocks * sites_per_block;
@@ -1669,10 +1759,10 @@ void class_lanes(const rfim_batch *b, const rfim_batch::Class &c, std::vector<La
         la.nblocks = (ln.nblocks / 2) & ~7;
         lb.map = ln.map + la.nblocks;
         lb.nblocks = ln.nblocks - la.nblocks;
-        lanes.push_back({{la}, sites / 2, fused});
-        lanes.push_back({{lb}, sites / 2, fused});
+        lanes.push_back({c.mode, {la}, {}, sites / 2, fused});
+        lanes.push_back({c.mode, {lb}, {}, sites / 2, fused});
     } else {
-        lanes.push_back({{ln}, sites, fused});
+        lanes.push_back({c.mode, {ln}, {}, sites, fused});
     }
 }
 
@@ -1694,18 +1784,28 @@ int batch_segment(rfim_batch *b, int m, bool exch) {
     }
     const int nq = (int)qs.size();
     for (size_t i = 0; i < lanes.size(); ++i)
-        if (lanes[i].ln[0].mode == 1)
+        if (lanes[i].mode == 1)
             HIPCHK(rfim_dev::launch_resident(lanes[i].ln[0], m, exch ? 1 : 0, qs[i % nq]));
-    // lane by lane, and in a lane group by group: a group's half-sweeps
-    // follow one another on its stream
+    // lane by lane, and in a lane group by group (item by item for bit
+    // storage): a group's half-sweeps follow one another on its stream
     for (size_t i = 0; i < lanes.size(); ++i)
-        if (lanes[i].ln[0].mode == 0)
+        if (lanes[i].mode == 0)
             for (const rfim_dev::Launch &lg : lanes[i].ln)
                 for (int q = 0; q < m; ++q) {
                     const int e = exch && q == m - 1 && lanes[i].fused;
                     HIPCHK(rfim_dev::launch_stream_sweep(lg, 0, q, 0, qs[i % nq]));
                     HIPCHK(rfim_dev::launch_stream_sweep(lg, 1, q, e, qs[i % nq]));
                 }
+    for (size_t i = 0; i < lanes.size(); ++i)
+        if (lanes[i].mode == rfim_dev::kModeBits)
+            for (const BitsPart &bp : lanes[i].parts) {
+                const Lattice lat = b->items[bp.item]->lattice();
+                for (int q = 0; q < m; ++q) {
+                    const int e = exch && q == m - 1;
+                    HIPCHK(rfim_dev::launch_bits_sweep(lat, bp.r0, bp.nrep, 0, q, 0, qs[i % nq]));
+                    HIPCHK(rfim_dev::launch_bits_sweep(lat, bp.r0, bp.nrep, 1, q, e, qs[i % nq]));
+                }
+            }
     for (int j = 0; j < nside; ++j) {
         HIPCHK(hipEventRecord(b->ev_join[j], b->aux[j]));
         HIPCHK(hipStreamWaitEvent(b->stream, b->ev_join[j], 0));
@@ -1748,7 +1848,8 @@ bool batch_prefers_graph(const rfim_batch *b, int every) {
         attempts += per_sweep * every;
         lanes.clear();
         class_lanes(b, c, lanes);
-        for (const Lane &l : lanes) launches += c.mode == 1 ? 1 : 2ll * every * (long long)l.ln.size();
+        for (const Lane &l : lanes)
+            launches += l.mode == 1 ? 1 : 2ll * every * (long long)(l.mode == 0 ? l.ln.size() : l.parts.size());
     }
     return attempts < kEagerAttemptsPerLaunch * launches;
 }
@@ -1889,24 +1990,23 @@ rfim_t *rfim_batch_item(rfim_batch_t *b, int i) {
 
 int rfim_batch_set_shape(rfim_batch_t *b, int L, int field_kind, int mode, int nw, int wg) {
     if (!b) return fail(RFIM_EINVAL, "batch is NULL");
-    if (mode >= 2) return fail(RFIM_EINVAL, "slab shapes are for single realizations");
-    if (!rfim_dev::shape_valid(L, mode, nw, wg))
-        return fail(RFIM_EINVAL, "launch shape (%d, %d, %d) not valid for L=%d", mode, nw, wg, L);
+    int rc = check_class_shape(L, mode, nw, wg);
+    if (rc) return rc;
     HIPCHK(hipStreamSynchronize(b->stream));
     for (auto &c : b->classes) {
         if (c.L != L || c.kind != field_kind) continue;
+        for (int i : c.members)
+            if ((rc = item_apply_shape(b->items[i], mode, nw, wg))) {
+                // back to the class's shape for the members already switched
+                const std::string msg = g_error;
+                for (int j : c.members) (void)item_apply_shape(b->items[j], c.mode, c.nw, c.wg);
+                (void)batch_build(b);
+                g_error = msg;
+                return rc;
+            }
         c.mode = mode;
-        c.nw = nw;
-        c.wg = wg;
-        for (int i : c.members) {
-            rfim *h = b->items[i];
-            h->mode = mode;
-            h->nw = nw;
-            h->wg = wg;
-            h->nblk = rfim_dev::blocks_per_replica(h->L, mode, nw, wg);
-            int rc = sync_descriptor(h);
-            if (rc) return rc;
-        }
+        c.nw = mode == rfim_dev::kModeBits ? 0 : nw;
+        c.wg = mode == rfim_dev::kModeBits ? 0 : wg;
     }
     return batch_build(b);
 }
@@ -1998,8 +2098,17 @@ struct rfim_pool {
 
 namespace {
 
-// Device bytes one realization reserves (what alloc_device allocates).
-size_t device_bytes(int L, int R_cap, int kind) { return arena_layout(L, R_cap, kind).total; }
+// Device bytes one realization reserves: what alloc_device allocates and,
+// at the L that bit storage takes, the bit arrays a bit-storage class
+// shape adds (the spin bits and the fields in the bit sweep's order).
+size_t device_bytes(int L, int R_cap, int kind) {
+    size_t n = arena_layout(L, R_cap, kind).total;
+    if (rfim_dev::bits_valid(L)) {
+        const size_t N = (size_t)L * L * L;
+        n += (size_t)R_cap * N / 8 + (kind == 0 ? N / 8 : N * sizeof(float));
+    }
+    return n;
+}
 
 rfim_pool::Shape &pool_shape(rfim_pool *p, int L, int kind) {
     for (auto &s : p->shapes)
@@ -2013,11 +2122,7 @@ rfim_pool::Shape &pool_shape(rfim_pool *p, int L, int kind) {
 int pool_apply_shape(rfim_pool *p, rfim *h) {
     const rfim_pool::Shape &s = pool_shape(p, h->L, h->kind);
     if (h->mode == s.mode && h->nw == s.nw && h->wg == s.wg) return RFIM_OK;
-    h->mode = s.mode;
-    h->nw = s.nw;
-    h->wg = s.wg;
-    h->nblk = rfim_dev::blocks_per_replica(h->L, s.mode, s.nw, s.wg);
-    return sync_descriptor(h);
+    return item_apply_shape(h, s.mode, s.nw, s.wg);
 }
 
 // Compact the active items, regroup them into classes and rebuild the
@@ -2234,9 +2339,8 @@ size_t rfim_pool_reserved(const rfim_pool_t *p) { return p ? p->reserved : 0; }
 
 int rfim_pool_set_shape(rfim_pool_t *p, int L, int field_kind, int mode, int nw, int wg) {
     if (!p) return fail(RFIM_EINVAL, "pool is NULL");
-    if (mode >= 2) return fail(RFIM_EINVAL, "slab shapes are for single realizations");
-    if (!rfim_dev::shape_valid(L, mode, nw, wg))
-        return fail(RFIM_EINVAL, "launch shape (%d, %d, %d) not valid for L=%d", mode, nw, wg, L);
+    int rc = check_class_shape(L, mode, nw, wg);
+    if (rc) return rc;
     HIPCHK(hipStreamSynchronize(p->core.stream));
     rfim_pool::Shape &s = pool_shape(p, L, field_kind);
     s.mode = mode;

@@ -64,8 +64,15 @@ struct Lattice {
     // colour c, word w = sublattice indices 32w..32w+31 (index 32w+4b+q at
     // bit 8q+b), 1 iff s = +1; fbw uint32 [2][N/64] in the same order,
     // 1 iff h_i = +1 (+-1 fields).  Null while the spins live in `spins`.
+    // fhw float [2][N/2]: continuous fields as in fhf, ordered for the bit
+    // sweep: in colour c, the four values of sublattice indices
+    // 32w+4b..32w+4b+3 (block b of word w) are float4 number
+    // (8 (w/64) + b) 64 + w%64, so that the 64 threads of a wavefront read
+    // block b of their words as 1 KiB in one piece (N/64 is a multiple of
+    // 64 at every L that bit storage takes).
     uint32_t *bits;
     const uint32_t *fbw;
+    const float *fhw;
 };
 
 // Above this many workgroups per replica the streaming sweep does not write
@@ -79,6 +86,11 @@ constexpr int kMaxFusedBlocks = 1024;
 // replica, mode - 1 sweeps per launch, wg threads).  Other L: generic
 // kernel, shape (0, 0, 0).  Every shape gives bit-identical results.
 bool shape_valid(int L, int mode, int nw, int wg);
+// Batch and pool classes also take shape (kModeBits, 0, 0) at L = 64, 128
+// or 256: one bit per spin, each item swept on its own by the bit sweep
+// (the storage of a standalone handle is set with rfim_set_spin_storage
+// instead).
+constexpr int kModeBits = 5;
 // Energy partials per replica for a shape (1 for resident, the workgroups
 // per replica when the streaming sweep fuses the energy, else 64).
 int blocks_per_replica(int L, int mode, int nw, int wg);

@@ -1122,9 +1122,10 @@ __global__ __launch_bounds__(kBitsThreads) void sweep_bits(Lattice lat, int colo
     if (KIND == 0) {
         F = gptr(lat.fbw)[(size_t)c * W1 + w];
     } else {
-        GAS const f32x4 *hf = (GAS const f32x4 *)(gptr(lat.fhf) + (size_t)c * lat.half + 32u * w);
+        GAS const f32x4 *hf = (GAS const f32x4 *)(gptr(lat.fhw) + (size_t)c * lat.half) +
+                              (size_t)(w >> 6) * 512u + (w & 63u);
 #pragma unroll
-        for (int b = 0; b < 8; ++b) HF[b] = hf[b];
+        for (int b = 0; b < 8; ++b) HF[b] = hf[b * 64];
     }
     __builtin_amdgcn_sched_barrier(0);
     const int slot = gptr(lat.r2t)[r];
@@ -1233,6 +1234,14 @@ __global__ __launch_bounds__(256) void pack_bits_kernel(Lattice lat) {
 #pragma unroll
         for (uint32_t i = 0; i < 32; ++i) f |= (uint32_t)((fb[i] >> 2) & 1u) << bit_of_index(i);
         ((uint32_t *)lat.fbw)[e] = f;
+    }
+    if (e < 2u * W1 && lat.kind == 1) {
+        // word w of colour c: its eight float4 blocks to the bit sweep's order
+        const uint32_t c = e / W1, w = e - c * W1;
+        const f32x4 *src4 = (const f32x4 *)(lat.fhf + (size_t)c * lat.half) + (size_t)w * 8u;
+        f32x4 *dst4 = (f32x4 *)(lat.fhw + (size_t)c * lat.half) + (size_t)(w >> 6) * 512u + (w & 63u);
+#pragma unroll
+        for (uint32_t b = 0; b < 8; ++b) dst4[b * 64u] = src4[b];
     }
 }
 

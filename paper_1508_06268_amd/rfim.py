@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_PKG, "librfim.so")
 RFIM_OK, RFIM_EINVAL, RFIM_ENOMEM, RFIM_EDEVICE, RFIM_ESTATE, RFIM_ECAP, RFIM_EBUSY = 0, -1, -2, -3, -4, -5, -6
 FIELDS_AUTO, FIELDS_BIMODAL, FIELDS_CONTINUOUS = -1, 0, 1
 MEASURE_FOURIER = 1
+# Batch and pool class shape (MODE_BITS, 0, 0): one bit per spin (L = 64, 128, 256)
+MODE_BITS = 5
 
 # Every symbol include/rfim.h declares (checked by the CPU tests).
 EXPORTS = [

@@ -27,7 +27,14 @@ def test_candidate_shapes():
     for L in (8, 16, 32, 64, 128):
         shapes = autotune.candidate_shapes(L)
         assert shapes, L
+        # bit storage is a candidate exactly where it is valid, tried first
+        assert ((autotune.MODE_BITS, 0, 0) in shapes) == (L in (64, 128)), L
+        if L >= 64:
+            assert shapes[0] == (autotune.MODE_BITS, 0, 0)
         for mode, nw, wg in shapes:
+            if mode == autotune.MODE_BITS:
+                assert (nw, wg) == (0, 0)
+                continue
             assert nw in (1, 2, 4, 8) and 4 * nw <= L // 2
             assert mode in (0, 1)
             if mode == 1:

@@ -230,3 +230,87 @@ def test_large_streaming_class_in_groups_equals_single_runs(rfim_mod):
     assert accepted > 0
     b.close()
     flat.close()
+
+
+def _l64_mix(Rs, tag):
+    """L=64 items of both field kinds with the given replica counts, and one
+    small L=16 item beside them."""
+    out = []
+    for rho, (R, kind) in enumerate([(R, "b") for R in Rs] + [(R, "g") for R in Rs] + [(8, "g")]):
+        L = 16 if rho == 2 * len(Rs) else 64
+        f = W.bimodal_fields(L, [tag, rho]) if kind == "b" else W.gaussian_fields(L, [tag, rho])
+        out.append(W.Realization(L=L, R=R, J=1.0, h=1.5 + 0.25 * rho, fields=f,
+                                 temps=W.geometric_temps(R, 1.0, 6.0), seed=13, realization=rho,
+                                 sweeps=0, every=10))
+    return out
+
+
+@pytest.mark.parametrize("Rs", [(4, 6), (128,), (128, 96)])
+def test_bit_storage_class_equals_single_runs(rfim_mod, Rs):
+    """A class in bit storage (MODE_BITS): its items are swept item by item
+    on one lane, or on two lanes (one item's replica halves for Rs = (128,),
+    the items themselves for (128, 96)).  Each item equals the same
+    realization run alone, bit for bit, also after the class goes back to a
+    byte shape."""
+    B = rfim_mod.rfim
+    mix = _l64_mix(Rs, 31)
+    b = rfim_mod.Batch(mix)
+    for kind in (B.FIELDS_BIMODAL, B.FIELDS_CONTINUOUS):
+        b.set_shape(64, kind, rfim_mod.MODE_BITS, 0, 0)
+    for q, w in enumerate(mix):
+        it = b.item(q)
+        want = (B.SPINS_BITS, (rfim_mod.MODE_BITS, 0, 0)) if w.L == 64 else (B.SPINS_BYTES, it.launch_shape())
+        assert (it.spin_storage(), it.launch_shape()) == want, q
+    for n, every in ((25, 10), (7, 10), (8, 10)):       # graph replays and ragged segments
+        b.sweep(n, every)
+    b.synchronize()
+    singles = []
+    for q, w in enumerate(mix):
+        g = _alone(rfim_mod, w, 40, 10)
+        it = b.item(q)
+        assert np.array_equal(it.spins(), g.spins()), q
+        assert np.array_equal(it.perm(), g.perm()), q
+        assert it.counters() == g.counters() == (40, 4)
+        assert np.array_equal(it.energies(), g.energies()), q      # both in bit storage at L=64
+        assert np.array_equal(it.exchange_stats()[1], g.exchange_stats()[1]), q
+        singles.append(g)
+    for kind in (B.FIELDS_BIMODAL, B.FIELDS_CONTINUOUS):
+        b.set_shape(64, kind, 0, 4, 128)
+    b.sweep(10, 10)
+    b.synchronize()
+    for q, (w, g) in enumerate(zip(mix, singles)):
+        it = b.item(q)
+        if w.L == 64:
+            assert (it.spin_storage(), it.launch_shape()) == (B.SPINS_BYTES, (0, 4, 128)), q
+        g.sweep(10, 10)
+        assert np.array_equal(it.spins(), g.spins()), q
+        assert np.array_equal(it.perm(), g.perm()), q
+        assert np.allclose(it.energies(), g.energies(), rtol=1e-12, atol=1e-9), q
+        g.close()
+    b.close()
+
+
+def test_bit_storage_class_shape_checks(rfim_mod):
+    """Bit storage needs L = 64, 128 or 256 and the shape (MODE_BITS, 0, 0);
+    its items refuse the Fourier measurement and a storage switch of their
+    own (the class shape decides)."""
+    B = rfim_mod.rfim
+    mix = _l64_mix((2,), 32)
+    b = rfim_mod.Batch(mix)
+    with pytest.raises(B.RfimError):
+        b.set_shape(16, B.FIELDS_CONTINUOUS, rfim_mod.MODE_BITS, 0, 0)
+    with pytest.raises(B.RfimError):
+        b.set_shape(64, B.FIELDS_BIMODAL, rfim_mod.MODE_BITS, 4, 128)
+    b.set_shape(64, B.FIELDS_BIMODAL, rfim_mod.MODE_BITS, 0, 0)
+    it = b.item(0)
+    with pytest.raises(B.RfimError):
+        it.set_measure(rfim_mod.MEASURE_FOURIER)
+    with pytest.raises(B.RfimError):
+        it.set_spin_storage(B.SPINS_BYTES)
+    assert it.spin_storage() == B.SPINS_BITS
+    b.sweep(10, 10)
+    b.synchronize()
+    g = _alone(rfim_mod, mix[0], 10, 10)
+    assert np.array_equal(it.spins(), g.spins())
+    g.close()
+    b.close()

@@ -68,7 +68,7 @@ def test_bits_continuous_fields_equal_byte_sweep(rfim_mod, L, R):
     T = W.geometric_temps(R, 1.0, 6.0)
     a = rfim_mod.Rfim(L, R, 1.0, 2.0, f, T, seed=3)
     b = rfim_mod.Rfim(L, R, 1.0, 2.0, f, T, seed=3)
-    a.set_spin_storage(rfim_mod.rfim.SPINS_BYTES)      # L = 128, 256 start in bits
+    a.set_spin_storage(rfim_mod.rfim.SPINS_BYTES)      # L = 64..256 start in bits
     b.set_spin_storage(rfim_mod.rfim.SPINS_BITS)
     assert a.spin_storage() == rfim_mod.rfim.SPINS_BYTES
     a.sweep(6, 3)
@@ -111,11 +111,11 @@ def test_bits_refuse_unsupported_sizes(rfim_mod, L):
 
 
 def test_default_storage_and_switches_to_bytes(rfim_mod):
-    """+-1 fields at L = 64..256 and Gaussian fields at L = 128, 256 start in
-    bits; Gaussian fields at L = 64 and other L in bytes; a launch shape, the
-    Fourier measurement or the tile order switch a handle to bytes."""
+    """Both field kinds start in bits at L = 64..256 and in bytes at other
+    L; a launch shape, the Fourier measurement or the tile order switch a
+    handle to bytes."""
     B = rfim_mod.rfim
-    for L, kind, want in ((64, "b", 1), (128, "b", 1), (64, "g", 0), (128, "g", 1), (32, "b", 0), (32, "g", 0)):
+    for L, kind, want in ((64, "b", 1), (128, "b", 1), (64, "g", 1), (128, "g", 1), (32, "b", 0), (32, "g", 0)):
         f = W.bimodal_fields(L, [88, L]) if kind == "b" else W.gaussian_fields(L, [88, L])
         g = rfim_mod.Rfim(L, 2, 1.0, 1.0, f, [1.0, 2.0], seed=1)
         assert g.spin_storage() == want, (L, kind)

@@ -13,11 +13,13 @@ from parity_util import make_pair
 pytestmark = pytest.mark.gpu
 
 
-def test_one_sweep_decision_mismatch_rate(rfim_mod, oracle_mod):
+@pytest.mark.parametrize("storage", ["bits", "bytes"])
+def test_one_sweep_decision_mismatch_rate(rfim_mod, oracle_mod, storage):
     L, R = 64, 40
     f = W.gaussian_fields(L, [0, 1])
     T = W.geometric_temps(R, 1.0, 6.0)
     g, o = make_pair(rfim_mod, oracle_mod, L, R, 1.0, 2.0, f, T, seed=0)
+    g.set_spin_storage(rfim_mod.rfim.SPINS_BITS if storage == "bits" else rfim_mod.rfim.SPINS_BYTES)
     total = 0
     mism = 0
     for rep in range(3):
@@ -28,7 +30,7 @@ def test_one_sweep_decision_mismatch_rate(rfim_mod, oracle_mod):
         o.sweep(1, 0)
         total += R * L ** 3
         mism += int((g.spins() != o.spins()).sum())
-    print("continuous-field decisions %d, mismatches %d" % (total, mism))
+    print("continuous-field decisions %d in %s, mismatches %d" % (total, storage, mism))
     assert total >= 10 ** 7
     assert mism / total < 1e-6
 
@@ -47,7 +49,7 @@ def test_energies_consistent_with_oracle_components(rfim_mod, oracle_mod):
     assert np.allclose(gf, of, rtol=1e-12, atol=1e-9)
 
 
-def _gpu_time_averages(rfim_mod, case, seeds, concurrency=0, shape=None):
+def _gpu_time_averages(rfim_mod, case, seeds, concurrency=0, shape=None, storage=None):
     """Per-seed time averages of E and |M| by slot over the measurement
     window of a case (same protocol as the oracle fixture: burn sweeps with
     an exchange every 10, then one sample after every exchange step of the
@@ -61,6 +63,8 @@ def _gpu_time_averages(rfim_mod, case, seeds, concurrency=0, shape=None):
         g = rfim_mod.Rfim(c["L"], c["R"], c["J"], c["h"], f, T, seed=seed)
         if shape is not None:
             g.set_launch_shape(*shape)
+        if storage is not None:
+            g.set_spin_storage(storage)
         if concurrency:
             g.set_concurrency(concurrency)
         g.sweep(c["burn"], c["every"])
@@ -74,12 +78,13 @@ def _gpu_time_averages(rfim_mod, case, seeds, concurrency=0, shape=None):
     return np.array(E), np.array(A)
 
 
-@pytest.mark.parametrize("case,set_name,concurrency,shape", [
-    ("l32", "l32_null", 0, None),            # L=32, R=64: the default slab shape
-    ("l32", "l32_null", 0, (1, 4, 1024)),    # the LDS-resident shape
-    ("l64", "l64_null", 2, None),            # L=64, R=8: streaming half-sweeps on two streams
+@pytest.mark.parametrize("case,set_name,concurrency,shape,storage", [
+    ("l32", "l32_null", 0, None, None),            # L=32, R=64: the default slab shape
+    ("l32", "l32_null", 0, (1, 4, 1024), None),    # the LDS-resident shape
+    ("l64", "l64_null", 2, None, 1),               # L=64, R=8: bit sweep, half-sweeps on two streams
+    ("l64", "l64_null", 2, None, 0),               # the same in byte storage (streaming kernel)
 ])
-def test_statistics_over_seeds(rfim_mod, case, set_name, concurrency, shape):
+def test_statistics_over_seeds(rfim_mod, case, set_name, concurrency, shape, storage):
     """32 GPU seeds against 32 disjoint oracle seeds (stored statistics from
     tests/golden/make_gaussian_stats.py): per slot, Welch's t on the
     time-averaged energy and |M|; the family of 2R comparisons must pass at
@@ -94,7 +99,7 @@ def test_statistics_over_seeds(rfim_mod, case, set_name, concurrency, shape):
     here = os.path.dirname(os.path.abspath(__file__))
     d = json.load(open(os.path.join(here, "golden", "gaussian_two_sample.json")))
     ref = d["sets"][set_name]
-    E, A = _gpu_time_averages(rfim_mod, case, range(1000, 1000 + d["nseeds"]), concurrency, shape)
+    E, A = _gpu_time_averages(rfim_mod, case, range(1000, 1000 + d["nseeds"]), concurrency, shape, storage)
     reject, pmin, thr, tmax = compare(summary(E), summary(A), from_json(ref["E"]), from_json(ref["absM"]))
     print("%s: GPU vs oracle seeds, p_min %.3g (threshold %.3g), max |t| %.2f" % (case, pmin, thr, tmax))
     assert not reject, (pmin, thr, tmax)

@@ -199,3 +199,29 @@ def test_pool_large_class_in_groups_equals_alone(rfim_mod):
         assert np.allclose(out.energies, g.energies(), rtol=1e-12, atol=1e-9), rq.rid
         assert np.array_equal(out.magnetizations, g.magnetizations()), rq.rid
         g.close()
+
+
+def test_pool_bit_storage_class_equals_alone(rfim_mod):
+    """The pool's L=64 classes in bit storage (MODE_BITS), with adaptive
+    insertion in place (R = 32 growing towards 48) and admissions while
+    others run; small L=16 requests beside them.  Each result must equal the
+    same realization run alone, which starts in bit storage at L=64."""
+    B = rfim_mod.rfim
+    specs = [(64, 32, "g"), (16, 16, "b"), (64, 32, "b"), (64, 40, "g"), (16, 8, "g"), (64, 32, "g")]
+    reqs = [_req(q, 0.003 * q, L, R, kind, trial=50, prod=100) for q, (L, R, kind) in enumerate(specs)]
+    shapes = {(64, B.FIELDS_BIMODAL): (rfim_mod.MODE_BITS, 0, 0), (64, B.FIELDS_CONTINUOUS): (rfim_mod.MODE_BITS, 0, 0)}
+    eng = PoolEngine(8 << 30, shapes=shapes)
+    res = Server(eng, quantum=50, every=10).run(reqs)
+    eng.close()
+    assert res["stats"]["completed"] == len(reqs), res["outcomes"]
+    grew = 0
+    for rq in reqs:
+        out = res["outcomes"][rq.rid]
+        g = _alone(rfim_mod, rq.spec)
+        assert out.R == g.R
+        grew += out.R > rq.spec.R
+        assert np.array_equal(out.perm, g.perm()), rq.rid
+        assert np.allclose(out.energies, g.energies(), rtol=1e-12, atol=1e-9), rq.rid
+        assert np.array_equal(out.magnetizations, g.magnetizations()), rq.rid
+        g.close()
+    assert grew > 0       # insertions happened
