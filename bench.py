@@ -287,6 +287,7 @@ def hbm_streaming_leg(torch, P, W, every=10, sweeps=200, reps=5, blocked=True):
 
     def run(group_bytes):
         b = P.Batch(specs, stream=stream)
+        b.set_shape(64, P.FIELDS_BIMODAL, 0, 4, 128)     # byte spins (L=64 classes start in bits)
         if group_bytes is not None:
             b.set_group_bytes(group_bytes)
         # graph capture and the first pass over the 512 MiB outside the

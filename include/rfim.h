@@ -334,8 +334,20 @@ int rfim_batch_synchronize(rfim_batch_t *b);
  * rfim_destroy ignores it; rfim_sweep, rfim_adapt_temps, rfim_set_counters
  * and rfim_set_launch_shape on it return RFIM_ESTATE. */
 rfim_t *rfim_batch_item(rfim_batch_t *b, int i);
-/* Launch shape of the class (L, field_kind) (see rfim_set_launch_shape);
- * used by the autotuner.  No effect on results. */
+/* Launch shape of the class (L, field_kind) (see rfim_set_launch_shape;
+ * modes 0 and 1), or RFIM_MODE_BITS: shape (RFIM_MODE_BITS, 0, 0) at L = 64,
+ * 128 or 256 keeps the class's items in one bit per spin (see
+ * rfim_set_spin_storage), each item swept on its own, all sweeps of an
+ * exchange interval before the next item of its stream (two streams from
+ * 2^23 sites of one colour per half, split by items or, for one item, by
+ * replicas); a byte shape takes them back to bytes.  Items in bit storage
+ * refuse the Fourier measurement and a storage switch of their own
+ * (RFIM_ESTATE).  Used by the autotuner.  No effect on results.  Classes
+ * at L = 64, 128 and 256 start in bit storage (in bytes if its arrays
+ * cannot be had), the others on the default launch shape of a single
+ * realization.  RFIM_EINVAL for slab or invalid shapes; RFIM_ENOMEM if bit
+ * arrays cannot be had (the class keeps its shape).  Synchronizes. */
+enum { RFIM_MODE_BITS = 5 };
 int rfim_batch_set_shape(rfim_batch_t *b, int L, int field_kind, int mode, int nw, int wg);
 /* Temporal blocking of large streaming classes (an optimisation of the
  * realization-level parallelism of Sec. 8; no effect on results).  A
@@ -367,7 +379,10 @@ typedef struct rfim_pool rfim_pool_t;
 rfim_pool_t *rfim_pool_create(size_t hbm_budget_bytes, void *hip_stream);
 void rfim_pool_destroy(rfim_pool_t *p);
 /* Device bytes a realization with these parameters reserves (0 if the
- * parameters are invalid). */
+ * parameters are invalid): its buffers at R_cap and, at L = 64, 128 or 256,
+ * the bit arrays a class in bit storage adds (R_cap L^3 / 8 bytes plus
+ * L^3 / 8 for +-1 fields or 4 L^3 for continuous fields), whatever the
+ * class shape. */
 size_t rfim_pool_bytes_needed(const rfim_params_t *params);
 /* Admit: a slot id >= 0, RFIM_EBUSY if the budget cannot hold it now (try
  * again after a release), or another negative status.  The slot has no
@@ -444,6 +459,9 @@ rfim_t *rfim_pool_item(rfim_pool_t *p, int slot);
 /* Slots admitted and not released (finished jobs included). */
 int rfim_pool_active(const rfim_pool_t *p);
 size_t rfim_pool_reserved(const rfim_pool_t *p);
+/* Shape of the class (L, field_kind) for items admitted from now on and,
+ * at the next step, for the items already there (see rfim_batch_set_shape,
+ * RFIM_MODE_BITS included; the same defaults).  Synchronizes. */
 int rfim_pool_set_shape(rfim_pool_t *p, int L, int field_kind, int mode, int nw, int wg);
 int rfim_pool_synchronize(rfim_pool_t *p);
 

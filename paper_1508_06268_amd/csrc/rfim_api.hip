@@ -1502,6 +1502,8 @@ struct rfim_batch {
 
 namespace {
 
+static_assert(rfim_dev::kModeBits == RFIM_MODE_BITS, "the class mode of bit storage is the ABI's");
+
 // A batch or pool item to its class shape: one bit per spin for
 // (kModeBits, 0, 0), byte spins with that launch shape otherwise.
 int item_apply_shape(rfim *h, int mode, int nw, int wg) {
@@ -1536,6 +1538,23 @@ int check_class_shape(int L, int mode, int nw, int wg) {
     return RFIM_OK;
 }
 
+// Every member of class c to shape (mode, nw, wg), and the class with them;
+// on failure the members go back to the class's shape.
+int class_apply_shape(rfim_batch *b, rfim_batch::Class &c, int mode, int nw, int wg) {
+    int rc;
+    for (int i : c.members)
+        if ((rc = item_apply_shape(b->items[i], mode, nw, wg))) {
+            const std::string msg = g_error;
+            for (int j : c.members) (void)item_apply_shape(b->items[j], c.mode, c.nw, c.wg);
+            g_error = msg;
+            return rc;
+        }
+    c.mode = mode;
+    c.nw = mode == rfim_dev::kModeBits ? 0 : nw;
+    c.wg = mode == rfim_dev::kModeBits ? 0 : wg;
+    return RFIM_OK;
+}
+
 void batch_free(rfim_batch *b) {
     if (!b) return;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
@@ -1566,14 +1585,10 @@ int batch_build(rfim_batch *b) {
     for (size_t ci = 0; ci < b->classes.size(); ++ci) {
         auto &c = b->classes[ci];
         std::vector<uint2> &map = maps[ci];
-        if (c.mode == rfim_dev::kModeBits) {    // launched item by item, no map
-            c.nblocks = 0;
-            continue;
-        }
         for (int i : c.members) {
             const rfim *h = b->items[i];
             const uint32_t hi = (uint32_t)i << 16;
-            if (c.mode == 1) {
+            if (c.mode == 1 || c.mode == rfim_dev::kModeBits) {     // one entry per replica
                 for (int r = 0; r < h->R; ++r) map.push_back(make_uint2(hi | (uint32_t)r, 0u));
             } else {
                 const int wpr = rfim_dev::stream_blocks_per_replica(c.L, c.nw, c.wg);
@@ -1624,15 +1639,9 @@ rfim_dev::Launch class_launch(const rfim_batch *b, const rfim_batch::Class &c) {
 // to the batch stream and up to kMaxSideStreams side streams.
 constexpr int kMaxSideStreams = 3;
 
-// Replicas r0 .. r0 + nrep - 1 of batch item `item` (bit storage).
-struct BitsPart {
-    int item, r0, nrep;
-};
-
 struct Lane {
     int mode;                           // the class's launch mode
     std::vector<rfim_dev::Launch> ln;   // one launch, or the groups of a large class in order
-    std::vector<BitsPart> parts;        // kModeBits: the items (or replica halves) in order
     long long work;
     bool fused;         // the class's sweep kernels write the energy partials
 };
@@ -1674,40 +1683,30 @@ int ensure_side_streams(rfim_batch *b, int n) {
 
 // The lanes of one class (see above and the two-lane split).
 void class_lanes(const rfim_batch *b, const rfim_batch::Class &c, std::vector<Lane> &lanes) {
+    const rfim_dev::Launch ln = class_launch(b, c);
     if (c.mode == rfim_dev::kModeBits) {
-        // each item runs all sweeps of the interval before the next item of
-        // its lane starts (its bits stay in the caches); two lanes from
-        // kSplitMinAttemptsBits sites per half, as for one realization
-        long long sites = 0;
-        for (int i : c.members) sites += (long long)b->items[i]->R * b->items[i]->half;
-        if (c.members.empty()) return;
-        if (sites / 2 < kSplitMinAttemptsBits) {
-            Lane l{c.mode, {}, {}, sites, true};
-            for (int i : c.members) l.parts.push_back({i, 0, b->items[i]->R});
-            lanes.push_back(l);
-        } else if (c.members.size() == 1) {
-            const int i = c.members[0], R = b->items[i]->R, ra = R / 2;
-            lanes.push_back({c.mode, {}, {{i, 0, ra}}, (long long)ra * b->items[i]->half, true});
-            lanes.push_back({c.mode, {}, {{i, ra, R - ra}}, (long long)(R - ra) * b->items[i]->half, true});
-        } else {
-            Lane la{c.mode, {}, {}, 0, true}, lb{c.mode, {}, {}, 0, true};
-            for (int i : c.members) {
-                const long long w = (long long)b->items[i]->R * b->items[i]->half;
-                Lane &l = la.parts.empty() || 2 * (la.work + w) <= sites ? la : lb;
-                l.parts.push_back({i, 0, b->items[i]->R});
-                l.work += w;
-            }
-            lanes.push_back(la);
-            if (!lb.parts.empty()) lanes.push_back(lb);
+        // one launch per half-sweep over every replica of the class (map
+        // entries are replicas), or two launches of half the replicas each
+        // on two lanes from kSplitMinAttemptsBits sites per half, as for
+        // one realization
+        const long long sites = (long long)ln.nblocks * c.L * c.L * c.L / 2;
+        if (ln.nblocks >= 2 && sites / 2 >= kSplitMinAttemptsBits) {
+            rfim_dev::Launch la = ln, lb = ln;
+            la.nblocks = ln.nblocks / 2;
+            lb.map = ln.map + la.nblocks;
+            lb.nblocks = ln.nblocks - la.nblocks;
+            lanes.push_back({c.mode, {la}, (long long)la.nblocks * c.L * c.L * c.L / 2, true});
+            lanes.push_back({c.mode, {lb}, (long long)lb.nblocks * c.L * c.L * c.L / 2, true});
+        } else if (ln.nblocks > 0) {
+            lanes.push_back({c.mode, {ln}, sites, true});
         }
         return;
     }
-    const rfim_dev::Launch ln = class_launch(b, c);
     const bool fused = class_fused(b, c);
     const long long sites = (long long)ln.nblocks * (c.mode == 1 ? (long long)c.L * c.L * c.L / 2
                                                                   : 4ll * c.nw * c.wg);
     if (c.mode != 0) {
-        lanes.push_back({c.mode, {ln}, {}, sites, fused});
+        lanes.push_back({c.mode, {ln}, sites, fused});
         return;
     }
     long long bytes = 0;
@@ -1745,7 +1744,7 @@ void class_lanes(const rfim_batch *b, const rfim_batch::Class &c, std::vector<La
         while (cut + 1 < groups.size() && 2 * (acc + gb[cut]) <= bytes) acc += gb[cut++];
         if (cut == 0) cut = 1;
         for (int side = 0; side < 2; ++side) {
-            Lane l{c.mode, {}, {}, 0, fused};
+            Lane l{c.mode, {}, 0, fused};
             for (size_t g = side ? cut : 0; g < (side ? groups.size() : cut); ++g) {
                 l.ln.push_back(groups[g]);
                 l.work += (long long)groups[g].nblocks * sites_per_block;
@@ -1759,10 +1758,10 @@ void class_lanes(const rfim_batch *b, const rfim_batch::Class &c, std::vector<La
         la.nblocks = (ln.nblocks / 2) & ~7;
         lb.map = ln.map + la.nblocks;
         lb.nblocks = ln.nblocks - la.nblocks;
-        lanes.push_back({c.mode, {la}, {}, sites / 2, fused});
-        lanes.push_back({c.mode, {lb}, {}, sites / 2, fused});
+        lanes.push_back({c.mode, {la}, sites / 2, fused});
+        lanes.push_back({c.mode, {lb}, sites / 2, fused});
     } else {
-        lanes.push_back({c.mode, {ln}, {}, sites, fused});
+        lanes.push_back({c.mode, {ln}, sites, fused});
     }
 }
 
@@ -1786,26 +1785,21 @@ int batch_segment(rfim_batch *b, int m, bool exch) {
     for (size_t i = 0; i < lanes.size(); ++i)
         if (lanes[i].mode == 1)
             HIPCHK(rfim_dev::launch_resident(lanes[i].ln[0], m, exch ? 1 : 0, qs[i % nq]));
-    // lane by lane, and in a lane group by group (item by item for bit
-    // storage): a group's half-sweeps follow one another on its stream
+    // lane by lane, and in a lane group by group: a group's half-sweeps
+    // follow one another on its stream
     for (size_t i = 0; i < lanes.size(); ++i)
-        if (lanes[i].mode == 0)
+        if (lanes[i].mode == 0 || lanes[i].mode == rfim_dev::kModeBits)
             for (const rfim_dev::Launch &lg : lanes[i].ln)
                 for (int q = 0; q < m; ++q) {
                     const int e = exch && q == m - 1 && lanes[i].fused;
-                    HIPCHK(rfim_dev::launch_stream_sweep(lg, 0, q, 0, qs[i % nq]));
-                    HIPCHK(rfim_dev::launch_stream_sweep(lg, 1, q, e, qs[i % nq]));
+                    if (lanes[i].mode == 0) {
+                        HIPCHK(rfim_dev::launch_stream_sweep(lg, 0, q, 0, qs[i % nq]));
+                        HIPCHK(rfim_dev::launch_stream_sweep(lg, 1, q, e, qs[i % nq]));
+                    } else {
+                        HIPCHK(rfim_dev::launch_bits_batch(lg, 0, q, 0, qs[i % nq]));
+                        HIPCHK(rfim_dev::launch_bits_batch(lg, 1, q, e, qs[i % nq]));
+                    }
                 }
-    for (size_t i = 0; i < lanes.size(); ++i)
-        if (lanes[i].mode == rfim_dev::kModeBits)
-            for (const BitsPart &bp : lanes[i].parts) {
-                const Lattice lat = b->items[bp.item]->lattice();
-                for (int q = 0; q < m; ++q) {
-                    const int e = exch && q == m - 1;
-                    HIPCHK(rfim_dev::launch_bits_sweep(lat, bp.r0, bp.nrep, 0, q, 0, qs[i % nq]));
-                    HIPCHK(rfim_dev::launch_bits_sweep(lat, bp.r0, bp.nrep, 1, q, e, qs[i % nq]));
-                }
-            }
     for (int j = 0; j < nside; ++j) {
         HIPCHK(hipEventRecord(b->ev_join[j], b->aux[j]));
         HIPCHK(hipStreamWaitEvent(b->stream, b->ev_join[j], 0));
@@ -1848,8 +1842,7 @@ bool batch_prefers_graph(const rfim_batch *b, int every) {
         attempts += per_sweep * every;
         lanes.clear();
         class_lanes(b, c, lanes);
-        for (const Lane &l : lanes)
-            launches += l.mode == 1 ? 1 : 2ll * every * (long long)(l.mode == 0 ? l.ln.size() : l.parts.size());
+        for (const Lane &l : lanes) launches += l.mode == 1 ? 1 : 2ll * every * (long long)l.ln.size();
     }
     return attempts < kEagerAttemptsPerLaunch * launches;
 }
@@ -1961,6 +1954,13 @@ rfim_batch_t *rfim_batch_create(int n, const rfim_params_t *items, void *hip_str
         h->wg = c.wg;
         h->nblk = rfim_dev::blocks_per_replica(h->L, c.mode, c.nw, c.wg);
     }
+    // classes at L = 64..256 start in bit storage, as single realizations
+    // do there (if its arrays cannot be had a class keeps byte spins)
+    for (auto &c : b->classes)
+        if (rfim_dev::bits_valid(c.L) && class_apply_shape(b, c, rfim_dev::kModeBits, 0, 0) != RFIM_OK) {
+            (void)hipGetLastError();
+            g_error.clear();
+        }
     hipError_t e = hipMalloc((void **)&b->d_lats, n * sizeof(Lattice));
     if (e != hipSuccess) {
         batch_free(b);
@@ -1995,18 +1995,12 @@ int rfim_batch_set_shape(rfim_batch_t *b, int L, int field_kind, int mode, int n
     HIPCHK(hipStreamSynchronize(b->stream));
     for (auto &c : b->classes) {
         if (c.L != L || c.kind != field_kind) continue;
-        for (int i : c.members)
-            if ((rc = item_apply_shape(b->items[i], mode, nw, wg))) {
-                // back to the class's shape for the members already switched
-                const std::string msg = g_error;
-                for (int j : c.members) (void)item_apply_shape(b->items[j], c.mode, c.nw, c.wg);
-                (void)batch_build(b);
-                g_error = msg;
-                return rc;
-            }
-        c.mode = mode;
-        c.nw = mode == rfim_dev::kModeBits ? 0 : nw;
-        c.wg = mode == rfim_dev::kModeBits ? 0 : wg;
+        if ((rc = class_apply_shape(b, c, mode, nw, wg))) {
+            const std::string msg = g_error;
+            (void)batch_build(b);
+            g_error = msg;
+            return rc;
+        }
     }
     return batch_build(b);
 }
@@ -2114,7 +2108,10 @@ rfim_pool::Shape &pool_shape(rfim_pool *p, int L, int kind) {
     for (auto &s : p->shapes)
         if (s.L == L && s.kind == kind) return s;
     rfim_pool::Shape s{L, kind, 0, 0, 0};
-    default_shape(L, 0, &s.mode, &s.nw, &s.wg);
+    if (rfim_dev::bits_valid(L))
+        s.mode = rfim_dev::kModeBits;       // bit storage, as for single realizations there
+    else
+        default_shape(L, 0, &s.mode, &s.nw, &s.wg);
     p->shapes.push_back(s);
     return p->shapes.back();
 }

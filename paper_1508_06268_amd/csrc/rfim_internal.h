@@ -145,6 +145,9 @@ int bits_blocks_per_replica(int L);
 // Half-sweep of colour `colour` at sweep t + toff for replicas r0..r0+nrep-1
 // (energy != 0 on colour 1: also the energy partials of the final state).
 hipError_t launch_bits_sweep(const Lattice &lat, int r0, int nrep, int colour, int toff, int energy, hipStream_t s);
+// The bit sweep over a batch class in bit storage: ln.map holds one entry
+// per replica (x = (realization << 16) | replica), ln.nblocks entries.
+hipError_t launch_bits_batch(const Launch &ln, int colour, int toff, int energy, hipStream_t s);
 // Byte spins <-> bit spins of replicas [0, R) (and, to bits, the +-1 field
 // words).
 hipError_t launch_pack_bits(const Lattice &lat, hipStream_t s);

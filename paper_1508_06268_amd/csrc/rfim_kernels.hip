@@ -1088,16 +1088,22 @@ constexpr int kBitsThreads = 256;
 
 __host__ __device__ constexpr int bits_wg(int L) { return L == 64 ? 128 : 256; }
 
-template <int KIND, int ENERGY>
-__global__ __launch_bounds__(kBitsThreads) void sweep_bits(Lattice lat, int colour, int toff, int r0, int lbpr,
-                                                          int remap) {
+// BATCH: the replicas of several realizations that share L and the field
+// kind, one map entry per replica (x = (realization << 16) | replica) and
+// 2^lbpr workgroups each; else replicas r0.. of lat0.
+template <int KIND, int ENERGY, bool BATCH>
+__global__ __launch_bounds__(kBitsThreads) void sweep_bits(Lattice lat0, const Lattice *__restrict__ lats,
+                                                          const uint2 *__restrict__ map, int colour, int toff,
+                                                          int r0, int lbpr, int remap) {
     __shared__ __align__(16) uint32_t sthr[32];   // +-1 thresholds or the continuous-field table
     uint32_t blk = blockIdx.x;
     if (remap) {
         const uint32_t per = gridDim.x >> 3;
         blk = (blk & 7u) * per + (blk >> 3);
     }
-    const uint32_t r = (uint32_t)r0 + (blk >> lbpr);
+    const uint32_t e = BATCH ? map[blk >> lbpr].x : 0u;
+    const Lattice &lat = BATCH ? lats[e >> 16] : lat0;
+    const uint32_t r = BATCH ? (e & 0xFFFFu) : (uint32_t)r0 + (blk >> lbpr);
     const uint32_t gb = blk & ((1u << lbpr) - 1u);
     const uint32_t L = (uint32_t)lat.L, l = (uint32_t)lat.log2L;
     const uint32_t W1 = (uint32_t)lat.N >> 6;            // words per colour
@@ -1774,21 +1780,35 @@ bool bits_valid(int L) { return L == 64 || L == 128 || L == 256; }
 
 int bits_blocks_per_replica(int L) { return (int)(((long long)L * L * L / 64) / bits_wg(L)); }
 
-hipError_t launch_bits_sweep(const Lattice &lat, int r0, int nrep, int colour, int toff, int energy, hipStream_t s) {
-    if (nrep <= 0) return hipSuccess;
-    const int bpr = bits_blocks_per_replica(lat.L);
+namespace {
+template <bool BATCH>
+void launch_bits(const Lattice &lat0, const Lattice *lats, const uint2 *map, int L, int kind, int r0, int nrep,
+                 int colour, int toff, int energy, hipStream_t s) {
+    const int bpr = bits_blocks_per_replica(L);
     const int lbpr = __builtin_ctz((unsigned)bpr);
     const int nb = bpr * nrep;
     const int remap = nb % 8 == 0 ? 1 : 0;
-    const dim3 grid((unsigned)nb), block((unsigned)bits_wg(lat.L));
+    const dim3 grid((unsigned)nb), block((unsigned)bits_wg(L));
     const bool e = energy && colour == 1;
-    if (lat.kind == 0) {
-        if (e) hipLaunchKernelGGL((sweep_bits<0, 1>), grid, block, 0, s, lat, colour, toff, r0, lbpr, remap);
-        else hipLaunchKernelGGL((sweep_bits<0, 0>), grid, block, 0, s, lat, colour, toff, r0, lbpr, remap);
+    if (kind == 0) {
+        if (e) hipLaunchKernelGGL((sweep_bits<0, 1, BATCH>), grid, block, 0, s, lat0, lats, map, colour, toff, r0, lbpr, remap);
+        else hipLaunchKernelGGL((sweep_bits<0, 0, BATCH>), grid, block, 0, s, lat0, lats, map, colour, toff, r0, lbpr, remap);
     } else {
-        if (e) hipLaunchKernelGGL((sweep_bits<1, 1>), grid, block, 0, s, lat, colour, toff, r0, lbpr, remap);
-        else hipLaunchKernelGGL((sweep_bits<1, 0>), grid, block, 0, s, lat, colour, toff, r0, lbpr, remap);
+        if (e) hipLaunchKernelGGL((sweep_bits<1, 1, BATCH>), grid, block, 0, s, lat0, lats, map, colour, toff, r0, lbpr, remap);
+        else hipLaunchKernelGGL((sweep_bits<1, 0, BATCH>), grid, block, 0, s, lat0, lats, map, colour, toff, r0, lbpr, remap);
     }
+}
+}  // namespace
+
+hipError_t launch_bits_sweep(const Lattice &lat, int r0, int nrep, int colour, int toff, int energy, hipStream_t s) {
+    if (nrep <= 0) return hipSuccess;
+    launch_bits<false>(lat, nullptr, nullptr, lat.L, lat.kind, r0, nrep, colour, toff, energy, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_bits_batch(const Launch &ln, int colour, int toff, int energy, hipStream_t s) {
+    if (ln.nblocks <= 0) return hipSuccess;
+    launch_bits<true>(Lattice{}, ln.lats, ln.map, ln.L, ln.kind, 0, ln.nblocks, colour, toff, energy, s);
     return hipGetLastError();
 }
 

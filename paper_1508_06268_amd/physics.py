@@ -15,7 +15,7 @@ import numpy as np
 
 from . import observables as ob
 from . import workloads as W
-from .rfim import MEASURE_FOURIER, Batch
+from .rfim import FIELDS_BIMODAL, MEASURE_FOURIER, Batch
 
 
 def binder_study(Ls: Sequence[int], realizations, temps: np.ndarray, h: float = 1.0,
@@ -33,6 +33,12 @@ def binder_study(Ls: Sequence[int], realizations, temps: np.ndarray, h: float = 
                                        realization=(L << 16) | q, sweeps=equilibration + measure,
                                        every=every))
     b = Batch(specs, stream=stream)
+    if correlation:
+        # the Fourier measurement reads byte spins: classes that start in
+        # bit storage (L = 64, 128, 256) take the streaming byte shape
+        for L in Ls:
+            if L in (64, 128, 256):
+                b.set_shape(L, FIELDS_BIMODAL, 0, 4, 128)
     b.sweep(equilibration, every)
     b.synchronize()
     for q in range(len(specs)):

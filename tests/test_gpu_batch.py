@@ -197,7 +197,8 @@ def test_large_streaming_class_in_groups_equals_single_runs(rfim_mod):
     before the next on its stream: 7 realizations of L=64, R=128 (32 MiB of
     byte spins each) form groups of 3, 3 and 1, the lanes [3] and [3, 1].
     Every item equals the same realization run alone, both field kinds,
-    with accepted exchanges."""
+    with accepted exchanges.  (Byte shapes set here: classes at L=64 start
+    in bit storage.)"""
     specs = []
     for rho in range(7):
         L, R = 64, 128
@@ -205,12 +206,17 @@ def test_large_streaming_class_in_groups_equals_single_runs(rfim_mod):
         specs.append(W.Realization(L=L, R=R, J=1.0, h=1.0, fields=f,
                                    temps=W.linear_temps(R, 4.0, 4.0 + 0.0002 * (R - 1)), seed=13,
                                    realization=rho, sweeps=0, every=3))
+    B = rfim_mod.rfim
     b = rfim_mod.Batch(specs)
+    for kind in (B.FIELDS_BIMODAL, B.FIELDS_CONTINUOUS):
+        b.set_shape(64, kind, 0, 4, 128)
     assert b.group_bytes() == 96 << 20
     b.sweep(3, 3)            # graph capture or eager, whichever the batch takes
     b.sweep(6, 3)
     b.synchronize()
     flat = rfim_mod.Batch(specs)
+    for kind in (B.FIELDS_BIMODAL, B.FIELDS_CONTINUOUS):
+        flat.set_shape(64, kind, 0, 4, 128)
     flat.set_group_bytes(0)  # no temporal blocking: every half-sweep over the whole class
     flat.sweep(9, 3)
     flat.synchronize()
@@ -297,6 +303,11 @@ def test_bit_storage_class_shape_checks(rfim_mod):
     B = rfim_mod.rfim
     mix = _l64_mix((2,), 32)
     b = rfim_mod.Batch(mix)
+    # the default: bit storage at L=64, the resident shape at L=16
+    assert [b.item(q).spin_storage() for q in range(3)] == [B.SPINS_BITS, B.SPINS_BITS, B.SPINS_BYTES]
+    assert b.item(1).launch_shape() == (rfim_mod.MODE_BITS, 0, 0)
+    b.set_shape(64, B.FIELDS_BIMODAL, 0, 4, 128)
+    assert b.item(0).spin_storage() == B.SPINS_BYTES
     with pytest.raises(B.RfimError):
         b.set_shape(16, B.FIELDS_CONTINUOUS, rfim_mod.MODE_BITS, 0, 0)
     with pytest.raises(B.RfimError):

@@ -187,7 +187,7 @@ def test_pool_large_class_in_groups_equals_alone(rfim_mod):
     (temporal blocking), rebuilt after every insertion.  Each result must
     equal the same realization run alone."""
     reqs = [_req(q, 0.0, 64, 128, "g", trial=50, prod=50) for q in range(7)]
-    eng = PoolEngine(8 << 30)
+    eng = PoolEngine(8 << 30, shapes={(64, 1): (0, 4, 128)})     # bytes (L=64 defaults to bits)
     res = Server(eng, quantum=50, every=10).run(reqs)
     eng.close()
     assert res["stats"]["completed"] == len(reqs), res["outcomes"]
@@ -202,7 +202,8 @@ def test_pool_large_class_in_groups_equals_alone(rfim_mod):
 
 
 def test_pool_bit_storage_class_equals_alone(rfim_mod):
-    """The pool's L=64 classes in bit storage (MODE_BITS), with adaptive
+    """The pool's L=64 classes in bit storage (MODE_BITS, also the default),
+    with adaptive
     insertion in place (R = 32 growing towards 48) and admissions while
     others run; small L=16 requests beside them.  Each result must equal the
     same realization run alone, which starts in bit storage at L=64."""
