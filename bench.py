@@ -47,13 +47,18 @@ BITS_BYTES_PER_ATTEMPT = 0.5
 TRAFFIC_BITS_FILE = os.path.join(ROOT, "profiles", "sweep_bits_l64_r192_traffic.txt")
 VALU_BITS_FILE = os.path.join(ROOT, "profiles", "sweep_bits_l64_r192_valu.txt")
 FIELD_BYTES = {0: 1.0, 1: 4.0}
-# Vector ALU issue: 256 CUs x 4 SIMDs, a wave64 instruction occupies its SIMD
-# for 4 cycles at full rate, so 256 x 4 x 2.4e9 / 4 = 0.614e12 wave-instruction
-# slots per second.  The VALU figure below counts the kernel's measured
-# VALU instructions per wave (profiles/sweep_pow2_l64_r192_valu.txt) at one
-# slot each.
+# Vector ALU issue: 256 CUs x 4 SIMDs at 2.4 GHz.  The published fp32 vector
+# peak, 157.3 TFLOP/s = 256 x 4 x 2.4e9 x 64 FLOP per cycle, is 32 fused
+# multiply-adds per SIMD and cycle: one wave64 32-bit instruction every two
+# cycles, 1.229e12 wave-instruction slots per second.  The fp64 peak (78.6)
+# is half that: an instruction with a 64-bit result (the Philox product,
+# v_mad_u64_u32) takes two slots; a transcendental (v_exp_f32) four.  A
+# kernel's slots per attempt: its VALU instructions from the committed
+# counters, plus one more per 64-bit product and three more per exponential
+# (both counted in the kernel's instruction stream, stated in the same
+# summary).
 CUS, SIMDS, CLOCK_HZ = 256, 4, 2.4e9
-WAVE_SLOTS_PER_S = CUS * SIMDS * CLOCK_HZ / 4.0
+WAVE_SLOTS_PER_S = CUS * SIMDS * CLOCK_HZ / 2.0
 
 
 def log(msg):
@@ -83,8 +88,15 @@ def measured_traffic(path):
 
 
 def measured_valu_per_1024(path):
-    """VALU wave-instructions per 1024 attempts of a sweep kernel."""
-    return _profile_value(path, r"VALU instructions per 1024 attempts:\s*([0-9.]+)")
+    """VALU issue slots per 1024 attempts of a sweep kernel (see
+    WAVE_SLOTS_PER_S): its VALU wave-instructions, one more slot per 64-bit
+    product and three more per exponential."""
+    ins = _profile_value(path, r"VALU instructions per 1024 attempts:\s*([0-9.]+)")
+    mad = _profile_value(path, r"64-bit products \(v_mad_u64_u32\) per 1024 attempts:\s*([0-9.]+)")
+    exp = _profile_value(path, r"exponentials \(v_exp_f32\) per 1024 attempts:\s*([0-9.]+)")
+    if ins is None or mad is None or exp is None:
+        return None
+    return ins + mad + 3.0 * exp
 
 
 def run_realization(h, w, stream, torch):
@@ -745,11 +757,11 @@ def main():
     if bits_legs and bits_legs["valu"]:
         rate, frac = alu_of(bits_legs["valu"], bits_legs["launch_us"])
         roofline = {"bound": "alu", "achieved": round(rate / 1e12, 4), "peak": round(WAVE_SLOTS_PER_S / 1e12, 4),
-                    "unit": "T wave-instructions/s", "frac": round(frac, 4),
+                    "unit": "T wave64 VALU slots/s", "frac": round(frac, 4),
                     "traffic": measured_traffic(TRAFFIC_BITS_FILE),
                     "kernel": "sweep_bits<bimodal>, one launch over R=%d" % R_final,
                     "launch_us": round(bits_legs["launch_us"], 3), "attempts_per_launch": attempts_per_launch,
-                    "valu_per_1024_attempts": bits_legs["valu"],
+                    "valu_slots_per_1024_attempts": bits_legs["valu"],
                     "attempts_per_ns_kernel": round(attempts_per_launch / (bits_legs["launch_us"] * 1e3), 1),
                     "hbm": {"achieved": round(bits_legs["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                             "frac": round(bits_legs["gbs"] / HBM_PEAK_GBS, 4),
@@ -758,7 +770,7 @@ def main():
                                     "attempts_per_ns": round(attempts_per_launch / (bits_legs["split_us"] * 1e3), 1),
                                     "alu_frac": round(alu_of(bits_legs["valu"], bits_legs["split_us"])[1], 4)},
                     "byte_kernel": byte_kernel}
-        log("VALU of the bit sweep: %.1f%% of issue (one launch), %.1f%% (two streams)"
+        log("VALU of the bit sweep: %.1f%% of the issue peak (one launch), %.1f%% (two streams)"
             % (100 * frac, 100 * roofline["two_streams"]["alu_frac"]))
     else:
         roofline = dict(byte_kernel)

@@ -1086,6 +1086,50 @@ __device__ __forceinline__ void class_offsets(uint32_t u0, uint32_t u1, uint32_t
 
 constexpr int kBitsThreads = 256;
 
+// Flip bits of one word of the bit sweep (its 32 sites, eight Philox
+// blocks), in the word's bit order.  NEV: the slot has classes that can
+// never flip (+-1 fields), checked per block; the common case runs
+// without that check.  (Interleaving the blocks' Philox chains by hand,
+// two, four or eight at a time, was no faster: the sweep is bound by
+// instruction issue, not by the chains' latency.)
+template <int KIND, bool NEV>
+__device__ __forceinline__ uint32_t word_flips(const uint32_t *sthr, uint32_t never, const uint32_t (&Acls)[8],
+                                               const f32x4 (&HF)[8], uint32_t w, uint32_t m0v, uint32_t c1w,
+                                               uint32_t r, uint32_t c3w, uint32_t key0, uint32_t key1) {
+    const uint8_t *tb = (const uint8_t *)sthr;
+    uint32_t flips = 0;
+#pragma unroll
+    for (uint32_t b = 0; b < 8; ++b) {
+        // block counters 8w + b: the first product M0 (8w + b) is one
+        // multiply-add of 8w with the constant M0 b
+        const Words rw = philox10_p(mad_m0(8u * w, m0v, (uint64_t)kPhiloxM0 * b), 8u * w + b, c1w, r, c3w,
+                                    key0, key1);
+        uint32_t acc;
+        if (KIND == 0) {
+            const uint32_t A = Acls[b];
+            const uint32_t a0 = A & 0xFFu, a1 = __builtin_amdgcn_ubfe(A, 8u, 8u), a2 = (A >> 16) & 0xFFu, a3 = A >> 24;
+            const uint32_t th0 = *(const uint32_t *)(tb + a0), th1 = *(const uint32_t *)(tb + a1);
+            const uint32_t th2 = *(const uint32_t *)(tb + a2), th3 = *(const uint32_t *)(tb + a3);
+            acc = accept_bits(rw.w0, rw.w1, rw.w2, rw.w3, th0, th1, th2, th3);
+            if (NEV) {
+                // a class that can never flip at this temperature has entry
+                // 0, which u = 0 would meet
+                const uint32_t umin = min(min(rw.w0, rw.w1), min(rw.w2, rw.w3));
+                if (umin == 0u) {
+                    if (rw.w0 == 0u && ((never >> (a0 >> 2)) & 1u)) acc &= ~1u;
+                    if (rw.w1 == 0u && ((never >> (a1 >> 2)) & 1u)) acc &= ~2u;
+                    if (rw.w2 == 0u && ((never >> (a2 >> 2)) & 1u)) acc &= ~4u;
+                    if (rw.w3 == 0u && ((never >> (a3 >> 2)) & 1u)) acc &= ~8u;
+                }
+            }
+        } else {
+            acc = continuous_acc_at(sthr, Acls[b], HF[b], rw);
+        }
+        flips |= nibble_to_bytes(acc) << b;
+    }
+    return flips;
+}
+
 __host__ __device__ constexpr int bits_wg(int L) { return L == 64 ? 128 : 256; }
 
 // BATCH: the replicas of several realizations that share L and the field
@@ -1158,40 +1202,15 @@ __global__ __launch_bounds__(kBitsThreads) void sweep_bits(Lattice lat0, const L
     const uint32_t U0 = s1 ^ s2, c3 = s1 & s2;
     const uint32_t U1 = xor3(c1, c2, c3), U2 = maj3(c1, c2, c3);
     const uint32_t c1w = 2u * t + c, c3w = (kTagSweep << 28) | lat.rho;
-    const uint8_t *tb = (const uint8_t *)sthr;
     uint32_t Acls[8];
     class_offsets(U0, U1, U2, S, KIND == 0 ? F : 0u, Acls);
     const uint32_t m0v = __builtin_amdgcn_readfirstlane(kPhiloxM0);   // held in one VGPR below
-    uint32_t flips = 0;
-#pragma unroll
-    for (uint32_t b = 0; b < 8; ++b) {
-        // block counters 8w + b: the first product M0 (8w + b) is one
-        // multiply-add of 8w with the constant M0 b
-        const Words rw = philox10_p(mad_m0(8u * w, m0v, (uint64_t)kPhiloxM0 * b), 8u * w + b, c1w, r, c3w,
-                                    lat.key0, lat.key1);
-        uint32_t acc;
-        if (KIND == 0) {
-            const uint32_t A = Acls[b];
-            const uint32_t a0 = A & 0xFFu, a1 = __builtin_amdgcn_ubfe(A, 8u, 8u), a2 = (A >> 16) & 0xFFu, a3 = A >> 24;
-            const uint32_t th0 = *(const uint32_t *)(tb + a0), th1 = *(const uint32_t *)(tb + a1);
-            const uint32_t th2 = *(const uint32_t *)(tb + a2), th3 = *(const uint32_t *)(tb + a3);
-            acc = accept_bits(rw.w0, rw.w1, rw.w2, rw.w3, th0, th1, th2, th3);
-            if (never != 0u) {
-                // a class that can never flip at this temperature has entry
-                // 0, which u = 0 would meet
-                const uint32_t umin = min(min(rw.w0, rw.w1), min(rw.w2, rw.w3));
-                if (umin == 0u) {
-                    if (rw.w0 == 0u && ((never >> (a0 >> 2)) & 1u)) acc &= ~1u;
-                    if (rw.w1 == 0u && ((never >> (a1 >> 2)) & 1u)) acc &= ~2u;
-                    if (rw.w2 == 0u && ((never >> (a2 >> 2)) & 1u)) acc &= ~4u;
-                    if (rw.w3 == 0u && ((never >> (a3 >> 2)) & 1u)) acc &= ~8u;
-                }
-            }
-        } else {
-            acc = continuous_acc_at(sthr, Acls[b], HF[b], rw);
-        }
-        flips |= nibble_to_bytes(acc) << b;
-    }
+    // `never` is the same for the whole workgroup: the common case (no class
+    // that can never flip) runs without the per-block check
+    const uint32_t flips =
+        KIND == 0 && never != 0u
+            ? word_flips<KIND, true>(sthr, never, Acls, HF, w, m0v, c1w, r, c3w, lat.key0, lat.key1)
+            : word_flips<KIND, false>(sthr, never, Acls, HF, w, m0v, c1w, r, c3w, lat.key0, lat.key1);
     const uint32_t Snew = S ^ flips;
     if (flips) own[w] = Snew;
     if (ENERGY) {
