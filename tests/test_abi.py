@@ -104,6 +104,10 @@ def test_pool_bytes_needed_accounts_every_buffer(rfim_mod, L, R, R_cap, kind):
     need = rfim_mod.Pool.bytes_needed(w)
     N = L ** 3
     assert need >= Rc * N + (N if kind == "b" else 8 * N)
+    if L in (64, 128, 256):
+        # the bit arrays a bit-storage class adds (spin bits, and the field bits
+        # or the reordered FP32 field copy) are reserved whatever the class shape
+        assert need >= Rc * N * 9 // 8 + (N + N // 8 if kind == "b" else 12 * N)
     assert need % 256 == 0
     bigger = W.Realization(L=L, R=R, J=1.0, h=1.0, fields=f, temps=W.linear_temps(R, 1.0, 5.0), seed=0,
                            sweeps=0, every=10, R_cap=Rc + 8)
