@@ -346,6 +346,30 @@ __device__ __forceinline__ uint32_t accept_bits(uint32_t u0, uint32_t u1, uint32
     return acc;
 }
 
+// The bit sweep's form: the four decisions of one Philox block shifted
+// into four accumulators, f_q = 2 f_q + [u_q <= t_q].  Run over blocks 7
+// down to 0, bit b of f_q ends as the flip of block b's site q, which is
+// bit 8q + b of the word: byte q of the flips is f_q, with no per-block
+// spreading.  Four compares and four add-with-carry per block; each mask
+// is read four instructions after it is written (gfx950's VALU-mask
+// hazard), and the trailing nop covers reads after the block.
+__device__ __forceinline__ void accept_shift(uint32_t u0, uint32_t u1, uint32_t u2, uint32_t u3,
+                                             uint32_t t0, uint32_t t1, uint32_t t2, uint32_t t3,
+                                             uint32_t &f0, uint32_t &f1, uint32_t &f2, uint32_t &f3) {
+    uint64_t c0, c1, c2, c3, cx;
+    asm("v_cmp_le_u32_e64 %4, %9, %13\n\t"
+        "v_cmp_le_u32_e64 %5, %10, %14\n\t"
+        "v_cmp_le_u32_e64 %6, %11, %15\n\t"
+        "v_cmp_le_u32_e64 %7, %12, %16\n\t"
+        "v_addc_co_u32_e64 %0, %8, %0, %0, %4\n\t"
+        "v_addc_co_u32_e64 %1, %8, %1, %1, %5\n\t"
+        "v_addc_co_u32_e64 %2, %8, %2, %2, %6\n\t"
+        "v_addc_co_u32_e64 %3, %8, %3, %3, %7\n\t"
+        "s_nop 1"
+        : "+v"(f0), "+v"(f1), "+v"(f2), "+v"(f3), "=&s"(c0), "=&s"(c1), "=&s"(c2), "=&s"(c3), "=&s"(cx)
+        : "v"(u0), "v"(u1), "v"(u2), "v"(u3), "v"(t0), "v"(t1), "v"(t2), "v"(t3));
+}
+
 // Metropolis decisions of one Philox block's four sites (+-1 fields): the
 // table entry sits at LDS byte address ((up << 2) | (s << 1) | f) * 4 and a
 // site flips iff u <= entry.  `never` marks classes whose bound is 0 at this
@@ -1042,15 +1066,6 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
 __device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);
 }
-constexpr uint32_t kByteLsb = 0x01010101u;
-// bits 0..3 of a to bit 0 of bytes 0..3: a 24-bit multiply written out, so
-// that a later shift is not folded into a constant the 24-bit form cannot
-// take
-__device__ __forceinline__ uint32_t nibble_to_bytes(uint32_t a) {
-    uint32_t r;
-    asm("v_mul_u32_u24 %0, %1, %2" : "=v"(r) : "s"(0x204081u), "v"(a));
-    return r & kByteLsb;
-}
 // position of sublattice index i (0..31) within its word
 __host__ __device__ constexpr uint32_t bit_of_index(uint32_t i) { return 8u * (i & 3u) + (i >> 2); }
 
@@ -1097,37 +1112,38 @@ __device__ __forceinline__ uint32_t word_flips(const uint32_t *sthr, uint32_t ne
                                                const f32x4 (&HF)[8], uint32_t w, uint32_t m0v, uint32_t c1w,
                                                uint32_t r, uint32_t c3w, uint32_t key0, uint32_t key1) {
     const uint8_t *tb = (const uint8_t *)sthr;
-    uint32_t flips = 0;
+    uint32_t f0 = 0, f1 = 0, f2 = 0, f3 = 0;
 #pragma unroll
-    for (uint32_t b = 0; b < 8; ++b) {
+    for (int b = 7; b >= 0; --b) {
         // block counters 8w + b: the first product M0 (8w + b) is one
         // multiply-add of 8w with the constant M0 b
-        const Words rw = philox10_p(mad_m0(8u * w, m0v, (uint64_t)kPhiloxM0 * b), 8u * w + b, c1w, r, c3w,
-                                    key0, key1);
-        uint32_t acc;
+        const Words rw = philox10_p(mad_m0(8u * w, m0v, (uint64_t)kPhiloxM0 * (uint32_t)b), 8u * w + b, c1w, r,
+                                    c3w, key0, key1);
+        const uint32_t A = Acls[b];
+        const uint32_t a0 = A & 0xFFu, a1 = __builtin_amdgcn_ubfe(A, 8u, 8u), a2 = (A >> 16) & 0xFFu, a3 = A >> 24;
         if (KIND == 0) {
-            const uint32_t A = Acls[b];
-            const uint32_t a0 = A & 0xFFu, a1 = __builtin_amdgcn_ubfe(A, 8u, 8u), a2 = (A >> 16) & 0xFFu, a3 = A >> 24;
             const uint32_t th0 = *(const uint32_t *)(tb + a0), th1 = *(const uint32_t *)(tb + a1);
             const uint32_t th2 = *(const uint32_t *)(tb + a2), th3 = *(const uint32_t *)(tb + a3);
-            acc = accept_bits(rw.w0, rw.w1, rw.w2, rw.w3, th0, th1, th2, th3);
+            accept_shift(rw.w0, rw.w1, rw.w2, rw.w3, th0, th1, th2, th3, f0, f1, f2, f3);
             if (NEV) {
                 // a class that can never flip at this temperature has entry
-                // 0, which u = 0 would meet
+                // 0, which u = 0 would meet: clear the bit just shifted in
                 const uint32_t umin = min(min(rw.w0, rw.w1), min(rw.w2, rw.w3));
                 if (umin == 0u) {
-                    if (rw.w0 == 0u && ((never >> (a0 >> 2)) & 1u)) acc &= ~1u;
-                    if (rw.w1 == 0u && ((never >> (a1 >> 2)) & 1u)) acc &= ~2u;
-                    if (rw.w2 == 0u && ((never >> (a2 >> 2)) & 1u)) acc &= ~4u;
-                    if (rw.w3 == 0u && ((never >> (a3 >> 2)) & 1u)) acc &= ~8u;
+                    if (rw.w0 == 0u && ((never >> (a0 >> 2)) & 1u)) f0 &= ~1u;
+                    if (rw.w1 == 0u && ((never >> (a1 >> 2)) & 1u)) f1 &= ~1u;
+                    if (rw.w2 == 0u && ((never >> (a2 >> 2)) & 1u)) f2 &= ~1u;
+                    if (rw.w3 == 0u && ((never >> (a3 >> 2)) & 1u)) f3 &= ~1u;
                 }
             }
         } else {
-            acc = continuous_acc_at(sthr, Acls[b], HF[b], rw);
+            const f32x4 hf = HF[b];
+            const uint32_t t0 = cont_bound(tb, a0, hf.x), t1 = cont_bound(tb, a1, hf.y);
+            const uint32_t t2 = cont_bound(tb, a2, hf.z), t3 = cont_bound(tb, a3, hf.w);
+            accept_shift(rw.w0, rw.w1, rw.w2, rw.w3, t0, t1, t2, t3, f0, f1, f2, f3);
         }
-        flips |= nibble_to_bytes(acc) << b;
     }
-    return flips;
+    return f0 | (f1 << 8) | (f2 << 16) | (f3 << 24);
 }
 
 __host__ __device__ constexpr int bits_wg(int L) { return L == 64 ? 128 : 256; }
