@@ -525,6 +525,10 @@ class Batch:
         _check(load_library().rfim_batch_synchronize(self._b))
 
     def set_shape(self, L, field_kind, mode, nw, wg):
+        """Launch shape of the class (L, field_kind) (rfim_batch_set_shape):
+        a streaming or LDS-resident shape in byte storage, or
+        (MODE_BITS, 0, 0), one bit per spin (L = 64, 128, 256; the default
+        there)."""
         _check(load_library().rfim_batch_set_shape(self._b, int(L), int(field_kind), int(mode),
                                                     int(nw), int(wg)))
 
@@ -662,6 +666,8 @@ class Pool:
         return int(load_library().rfim_pool_reserved(self._p))
 
     def set_shape(self, L, field_kind, mode, nw, wg):
+        """Shape of the class (L, field_kind) for its items (rfim_pool_set_shape;
+        see Batch.set_shape)."""
         _check(load_library().rfim_pool_set_shape(self._p, int(L), int(field_kind), int(mode), int(nw),
                                                    int(wg)))
 
