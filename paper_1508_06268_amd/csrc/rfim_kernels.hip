@@ -1101,6 +1101,13 @@ __device__ __forceinline__ void class_offsets(uint32_t u0, uint32_t u1, uint32_t
 
 constexpr int kBitsThreads = 256;
 
+// Word i of a colour's bit array, addressed as a wave-uniform base plus a
+// 32-bit byte offset (one vector register per load instead of a 64-bit
+// address; i < 2^30 at every L that bit storage takes).
+__device__ __forceinline__ uint32_t bits_word(GAS const uint32_t *base, uint32_t i) {
+    return *(GAS const uint32_t *)((GAS const char *)base + (i << 2));
+}
+
 // Flip bits of one word of the bit sweep (its 32 sites, eight Philox
 // blocks), in the word's bit order.  NEV: the slot has classes that can
 // never flip (+-1 fields), checked per block; the common case runs
@@ -1168,21 +1175,23 @@ __global__ __launch_bounds__(kBitsThreads) void sweep_bits(Lattice lat0, const L
     const uint32_t L = (uint32_t)lat.L, l = (uint32_t)lat.log2L;
     const uint32_t W1 = (uint32_t)lat.N >> 6;            // words per colour
     const uint32_t lrw = l - 6u, rw_ = 1u << lrw;        // words per row
+    // w = (z L + y) rw_ + wr: the bit fields of wr, y and z side by side, so
+    // a neighbour's word is w stepped inside one field and put back (the
+    // step's carry or borrow out of the field masked off: periodic wrap)
     const uint32_t w = gb * blockDim.x + threadIdx.x;
-    const uint32_t row = w >> lrw, wr = w & (rw_ - 1u);
-    const uint32_t y = row & (L - 1u), z = row >> l;
     const uint32_t c = (uint32_t)colour;
-    const uint32_t p = (c + y + z) & 1u;
+    const uint32_t p = (c + (w >> lrw) + (w >> (lrw + l))) & 1u;      // (c + y + z) mod 2
+    const uint32_t xm = rw_ - 1u, ym = (L - 1u) << lrw, zm = ym << l;
+    const uint32_t wx = ((w + 2u * p - 1u) & xm) | (w & ~xm);          // the word holding index m -+ 1
+    const uint32_t wyp = ((w + rw_) & ym) | (w & ~ym), wym = ((w - rw_) & ym) | (w & ~ym);
+    const uint32_t wzp = ((w + (rw_ << l)) & zm) | (w & ~zm), wzm = ((w - (rw_ << l)) & zm) | (w & ~zm);
     GAS uint32_t *own = gptr(lat.bits) + ((size_t)r * 2u + c) * W1;
     GAS const uint32_t *oth = gptr(lat.bits) + ((size_t)r * 2u + (1u - c)) * W1;
-    const uint32_t base = row << lrw;
-    const uint32_t S = own[w];
-    const uint32_t W = oth[w];
-    const uint32_t Wn = oth[base + ((wr + (p ? 1u : rw_ - 1u)) & (rw_ - 1u))];
-    const uint32_t Wyp = oth[((((y + 1u) & (L - 1u)) + (z << l)) << lrw) + wr];
-    const uint32_t Wym = oth[((((y - 1u) & (L - 1u)) + (z << l)) << lrw) + wr];
-    const uint32_t Wzp = oth[((y + (((z + 1u) & (L - 1u)) << l)) << lrw) + wr];
-    const uint32_t Wzm = oth[((y + (((z - 1u) & (L - 1u)) << l)) << lrw) + wr];
+    const uint32_t S = bits_word(own, w);
+    const uint32_t W = bits_word(oth, w);
+    const uint32_t Wn = bits_word(oth, wx);
+    const uint32_t Wyp = bits_word(oth, wyp), Wym = bits_word(oth, wym);
+    const uint32_t Wzp = bits_word(oth, wzp), Wzm = bits_word(oth, wzm);
     uint32_t F = 0;
     f32x4 HF[8];
     if (KIND == 0) {
@@ -1228,7 +1237,7 @@ __global__ __launch_bounds__(kBitsThreads) void sweep_bits(Lattice lat0, const L
             ? word_flips<KIND, true>(sthr, never, Acls, HF, w, m0v, c1w, r, c3w, lat.key0, lat.key1)
             : word_flips<KIND, false>(sthr, never, Acls, HF, w, m0v, c1w, r, c3w, lat.key0, lat.key1);
     const uint32_t Snew = S ^ flips;
-    if (flips) own[w] = Snew;
+    if (flips) *(GAS uint32_t *)((GAS char *)own + (w << 2)) = Snew;
     if (ENERGY) {
         // colour 1 of the last sweep before an exchange: the final state.
         // B counts each bond once through the colour-1 sites: sum of
