@@ -226,3 +226,40 @@ def test_pool_bit_storage_class_equals_alone(rfim_mod):
         assert np.array_equal(out.magnetizations, g.magnetizations()), rq.rid
         g.close()
     assert grew > 0       # insertions happened
+
+
+def test_pool_class_switches_storage_while_running(rfim_mod, oracle_mod):
+    """Live +-1 items at L=64 (bit storage by default) go to a byte shape and
+    back between steps, with an insertion step in between: each item's
+    storage follows the class shape at the next step, and every item still
+    equals the oracle's chain."""
+    B = rfim_mod.rfim
+    reqs = [_req(q, 0.0, 64, R, "b", trial=50, prod=50) for q, R in enumerate((6, 4))]
+    pool = rfim_mod.Pool(4 << 30)
+    slots = [pool.admit(r.spec) for r in reqs]
+    pool.step(20, 10)
+    assert all(pool.item(s).spin_storage() == B.SPINS_BITS for s in slots)
+    pool.set_shape(64, B.FIELDS_BIMODAL, 0, 4, 128)
+    pool.step(20, 10)
+    assert all(pool.item(s).spin_storage() == B.SPINS_BYTES for s in slots)
+    for s, r in zip(slots, reqs):
+        a = r.spec.adapt
+        pool.adapt(s, a["rate_threshold"], a["max_insert_per_trial"], a["R_cap"])
+    pool.set_shape(64, B.FIELDS_BIMODAL, rfim_mod.MODE_BITS, 0, 0)
+    pool.step(20, 10)
+    assert all(pool.item(s).spin_storage() == B.SPINS_BITS for s in slots)
+    pool.synchronize()
+    for s, r in zip(slots, reqs):
+        w = r.spec
+        o = oracle_mod.Oracle(w.L, w.R, w.J, w.h, w.fields, w.temps, seed=w.seed, realization=w.realization,
+                              R_cap=w.R_cap)
+        a = w.adapt
+        o.adapt_temps(1, 40, 10, a["rate_threshold"], a["max_insert_per_trial"], a["R_cap"])
+        o.sweep(20, 10)
+        it = pool.item(s)
+        assert it.R == o.R, s
+        assert np.array_equal(it.spins(), o.spins()), s
+        assert np.array_equal(it.perm(), o.perm()), s
+        assert np.array_equal(it.energies(), o.energies()), s
+        assert it.counters() == o.counters()
+    pool.close()
